@@ -1,0 +1,240 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle/rtgd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
+by the CPU-baseline leg of the benchmark.  The product path never imports it.
+It shares nothing with the GPU library except the seeded inputs the callers
+pass in.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "rtgd_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+GRID, CHAPMAN, QP, GRID_CR = 0, 1, 2, 3
+GROUND, ESCAPE, MAX_PATH, NUMERIC = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: FP64, no fast-math, no FMA contraction."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class Medium(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("n_lat", ctypes.c_int), ("n_lon", ctypes.c_int), ("n_h", ctypes.c_int),
+        ("lat0_deg", ctypes.c_double), ("dlat_deg", ctypes.c_double),
+        ("lon0_deg", ctypes.c_double), ("dlon_deg", ctypes.c_double),
+        ("h0_km", ctypes.c_double), ("dh_km", ctypes.c_double),
+        ("ne", ctypes.POINTER(ctypes.c_double)),
+        ("fc_mhz", ctypes.c_double), ("hm_km", ctypes.c_double),
+        ("thick_km", ctypes.c_double), ("floor_km", ctypes.c_double),
+    ]
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("B0_T", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("R_km", ctypes.c_double),
+        ("tx_lat_deg", ctypes.c_double), ("tx_lon_deg", ctypes.c_double),
+        ("tx_h_km", ctypes.c_double),
+        ("step_km", ctypes.c_double), ("max_group_km", ctypes.c_double),
+        ("exit_h_km", ctypes.c_double),
+        ("traj_stride", ctypes.c_int), ("nthreads", ctypes.c_int),
+    ]
+
+
+class Ham(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_double), ("G", ctypes.c_double),
+                ("Hn", ctypes.c_double * 3), ("Hq", ctypes.c_double * 3),
+                ("X", ctypes.c_double), ("mu2", ctypes.c_double)]
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.or_gd_weights.argtypes = [ctypes.c_double, _DP, _DP]
+        L.or_cr_weights.argtypes = [ctypes.c_double, _DP, _DP]
+        L.or_medium_eval.argtypes = [ctypes.POINTER(Medium), ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, _DP]
+        L.or_dipole.argtypes = [ctypes.c_double] * 5 + [_DP, _DP, _DP]
+        L.or_appleton.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, _DP]
+        L.or_appleton.restype = ctypes.c_int
+        L.or_hamiltonian.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field),
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, _DP,
+                                     ctypes.POINTER(Ham)]
+        L.or_hamiltonian.restype = ctypes.c_int
+        L.or_rhs.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field), ctypes.c_double,
+                             ctypes.c_double, ctypes.c_int, _DP, _DP]
+        L.or_rhs.restype = ctypes.c_int
+        L.or_launch.argtypes = [ctypes.POINTER(Opts), ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, _DP]
+        L.or_launch.restype = ctypes.c_double
+        L.or_trace.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field),
+                               ctypes.POINTER(Opts), ctypes.c_int, _DP, _DP, _DP, _IP, _DP,
+                               _IP, _IP, _DP, ctypes.c_int, _IP]
+        L.or_trace.restype = ctypes.c_longlong
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _ip(a):
+    return a.ctypes.data_as(_IP)
+
+
+class OracleMedium:
+    """Holds a Medium struct and keeps the grid array alive."""
+
+    def __init__(self, kind=GRID, grid=None, fc_mhz=0.0, hm_km=0.0, thick_km=0.0,
+                 floor_km=60.0):
+        self.m = Medium()
+        self.m.kind = kind
+        self._ne = None
+        if grid is not None:
+            g = grid.geom
+            self._ne = np.ascontiguousarray(grid.values, dtype=np.float64)
+            self.m.n_lat, self.m.n_lon, self.m.n_h = g.n_lat, g.n_lon, g.n_h
+            self.m.lat0_deg, self.m.dlat_deg = g.lat0_deg, g.dlat_deg
+            self.m.lon0_deg, self.m.dlon_deg = g.lon0_deg, g.dlon_deg
+            self.m.h0_km, self.m.dh_km = g.h0_km, g.dh_km
+            self.m.ne = _dp(self._ne)
+            floor_km = g.h0_km
+        self.m.fc_mhz, self.m.hm_km, self.m.thick_km = fc_mhz, hm_km, thick_km
+        self.m.floor_km = floor_km
+
+    @classmethod
+    def from_grid(cls, grid, interp="gd"):
+        return cls(GRID_CR if interp == "cr" else GRID, grid=grid)
+
+    @classmethod
+    def chapman(cls, fc_mhz, hm_km, scale_km, floor_km=60.0):
+        return cls(CHAPMAN, fc_mhz=fc_mhz, hm_km=hm_km, thick_km=scale_km, floor_km=floor_km)
+
+    @classmethod
+    def qp(cls, fc_mhz, hm_km, ym_km, floor_km=60.0):
+        return cls(QP, fc_mhz=fc_mhz, hm_km=hm_km, thick_km=ym_km, floor_km=floor_km)
+
+    def eval(self, R, r, th, ph):
+        out = np.zeros(4)
+        lib().or_medium_eval(ctypes.byref(self.m), R, r, th, ph, _dp(out))
+        return out
+
+
+def gd_weights(s):
+    w, dw = np.zeros(4), np.zeros(4)
+    lib().or_gd_weights(float(s), _dp(w), _dp(dw))
+    return w, dw
+
+
+def cr_weights(s):
+    w, dw = np.zeros(4), np.zeros(4)
+    lib().or_cr_weights(float(s), _dp(w), _dp(dw))
+    return w, dw
+
+
+def dipole(B0, R, f_mhz, r, th):
+    Y, Yr, Yt = np.zeros(3), np.zeros(3), np.zeros(3)
+    lib().or_dipole(B0, R, f_mhz, r, th, _dp(Y), _dp(Yr), _dp(Yt))
+    return Y, Yr, Yt
+
+
+def appleton(X, a, b, mode):
+    out = np.zeros(4)
+    ok = lib().or_appleton(X, a, b, mode, _dp(out))
+    return out, bool(ok)
+
+
+def hamiltonian(med: OracleMedium, B0, R, f_mhz, mode, y):
+    y = np.ascontiguousarray(y[:6], dtype=np.float64)
+    h = Ham()
+    fld = Field(B0)
+    ok = lib().or_hamiltonian(ctypes.byref(med.m), ctypes.byref(fld), R, f_mhz, mode,
+                              _dp(y), ctypes.byref(h))
+    return {"H": h.H, "G": h.G, "Hn": np.array(h.Hn[:]), "Hq": np.array(h.Hq[:]),
+            "X": h.X, "mu2": h.mu2, "ok": bool(ok)}
+
+
+def rhs(med: OracleMedium, B0, R, f_mhz, mode, y):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    dy = np.zeros(7)
+    fld = Field(B0)
+    lib().or_rhs(ctypes.byref(med.m), ctypes.byref(fld), R, f_mhz, mode, _dp(y), _dp(dy))
+    return dy
+
+
+def make_opts(R=6371.0, tx=(30.0, 110.0, 0.0), step=1.0, max_group=4000.0, exit_h=500.0,
+              traj_stride=0, nthreads=0):
+    return Opts(R, tx[0], tx[1], tx[2], step, max_group, exit_h, traj_stride, nthreads)
+
+
+def launch(opts: Opts, floor_km, elev, az):
+    y = np.zeros(7)
+    s = lib().or_launch(ctypes.byref(opts), floor_km, elev, az, _dp(y))
+    return y, s
+
+
+OUT_NAMES = ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km",
+             "land_lat_deg", "land_lon_deg")
+
+
+def trace(med: OracleMedium, elev, az, freq, mode=None, B0=0.0, R=6371.0,
+          tx=(30.0, 110.0, 0.0), step=1.0, max_group=4000.0, exit_h=500.0,
+          traj_stride=0, traj_per_ray=0, nthreads=0):
+    """Trace rays given per-ray elevation/azimuth (deg), frequency (MHz) and
+    mode (+1 O, -1 X).  Returns a dict of numpy arrays."""
+    elev = np.ascontiguousarray(elev, dtype=np.float64)
+    n = elev.size
+    az = np.ascontiguousarray(np.broadcast_to(az, (n,)), dtype=np.float64)
+    freq = np.ascontiguousarray(np.broadcast_to(freq, (n,)), dtype=np.float64)
+    if mode is None:
+        mode = np.ones(n, dtype=np.int32)
+    mode = np.ascontiguousarray(np.broadcast_to(mode, (n,)), dtype=np.int32)
+    out7 = np.zeros((n, 7))
+    status = np.zeros(n, dtype=np.int32)
+    nsteps = np.zeros(n, dtype=np.int32)
+    opts = make_opts(R, tx, step, max_group, exit_h, traj_stride, nthreads)
+    fld = Field(B0)
+    traj = tcount = None
+    if traj_stride > 0 and traj_per_ray > 0:
+        traj = np.zeros((n, traj_per_ray, 8))
+        tcount = np.zeros(n, dtype=np.int32)
+    total = lib().or_trace(ctypes.byref(med.m), ctypes.byref(fld), ctypes.byref(opts), n,
+                           _dp(elev), _dp(az), _dp(freq), _ip(mode), _dp(out7), _ip(status),
+                           _ip(nsteps), _dp(traj) if traj is not None else None,
+                           traj_per_ray, _ip(tcount) if tcount is not None else None)
+    res = {k: out7[:, i].copy() for i, k in enumerate(OUT_NAMES)}
+    res["status"] = status
+    res["n_steps"] = nsteps
+    res["total_steps"] = int(total)
+    if traj is not None:
+        res["traj"] = traj
+        res["traj_count"] = tcount
+    return res
