@@ -1,0 +1,188 @@
+/*
+ * rtgd.h -- C ABI of librtgd: batched HF ray tracing through a gridded
+ * ionosphere on one AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the hot path of RTM-GD ("Efficient and
+ * High-Accuracy Ray Tracing in Discretized Ionospheric Models"):
+ * many independent rays integrated with fixed-step RK4 (Sec. II-C) along the
+ * Haselgrove equations in spherical coordinates (Sec. II-A, eq. 1a-1f, with
+ * the frame term of the k_r equation taken as k_phi sin(theta) dphi/dP'),
+ * through an electron density reconstructed by the C1 Galerkin-Difference
+ * interpolant, p = 3 (Sec. II-B-2, eq. 3dinterp_gd, Appendix A), with the
+ * Appleton-Hartree refractive index (eq. appleton, collisionless, + = O,
+ * - = X) under a centred axial dipole field.
+ *
+ * Conventions shared by every call:
+ *   - lengths in km, angles in degrees, frequencies in MHz;
+ *   - spherical Earth of radius earth_radius_km; transmitter height must lie
+ *     below the grid bottom h0_km: rays run as straight lines through the
+ *     density-free region below h0_km (launch and ground return are closed
+ *     form), N_e = 0 below h0_km;
+ *   - outside the grid box laterally or above its top the density is
+ *     continued as a constant (its derivative along the clamped axis is 0);
+ *   - the wave-normal vector n = c k / omega is carried in local
+ *     (r, theta = colatitude, phi = east longitude) components.
+ *
+ * Errors: every call returns an rt_status; no C++ exception crosses the ABI.
+ * rt_last_error(ctx) returns a message for the last failed call on a context;
+ * rt_last_error(NULL) the message of the last failed rt_ctx_create on the
+ * calling thread.
+ * A context is used by one host thread at a time.
+ */
+#ifndef RTGD_H
+#define RTGD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rt_status;
+enum {
+    RT_OK = 0,
+    RT_W_TRAJ_TRUNCATED = 1, /* success; some trajectories did not fit     */
+    RT_E_INVALID = -1,       /* bad argument (message in rt_last_error)    */
+    RT_E_NOMEM = -2,         /* device allocation failed                   */
+    RT_E_DEVICE = -3,        /* HIP runtime error                          */
+    RT_E_UNSUPPORTED = -4    /* valid request outside what is implemented  */
+};
+
+/* element type / quantity of the grid values handed to rt_grid_create */
+enum { RT_F64 = 0, RT_F32 = 1 };
+enum { RT_NE_M3 = 0, RT_FN2_MHZ2 = 1 };   /* N_e in m^-3, or f_N^2 in MHz^2 */
+/* interpolation of the grid */
+enum { RT_INTERP_GD = 0, RT_INTERP_CR = 1 };
+/* wave modes (bit mask in rt_fan.modes) */
+enum { RT_MODE_O = 1, RT_MODE_X = 2 };
+/* arithmetic of the trace */
+enum { RT_FP64 = 0, RT_MIXED = 1 };
+/* where caller buffers live */
+enum { RT_MEM_HOST = 0, RT_MEM_DEVICE = 1 };
+/* per-ray termination status */
+enum { RT_RAY_GROUND = 0, RT_RAY_ESCAPE = 1, RT_RAY_MAX_PATH = 2, RT_RAY_NUMERIC = 3 };
+
+typedef struct rt_ctx rt_ctx;
+typedef struct rt_grid rt_grid;
+
+/* Uniform (lat, lon, height) grid.  Node (i, j, k) sits at
+ * lat0 + i dlat, lon0 + j dlon, h0 + k dh; values are C order
+ * [n_lat][n_lon][n_h] (height fastest).  Every n >= 4, every spacing > 0,
+ * the latitude range inside (-90, 90). */
+typedef struct {
+    int32_t n_lat, n_lon, n_h;
+    int32_t dtype;      /* RT_F64 or RT_F32                               */
+    int32_t quantity;   /* RT_NE_M3 or RT_FN2_MHZ2                        */
+    int32_t interp;     /* RT_INTERP_GD (the method) or RT_INTERP_CR      */
+    double lat0_deg, dlat_deg;
+    double lon0_deg, dlon_deg;
+    double h0_km, dh_km;
+    double earth_radius_km;
+} rt_grid_geom;
+
+/* Centred dipole.  B0 = field at the equator on the Earth's surface
+ * (|B| = B0 (R/r)^3 sqrt(1 + 3 cos^2 theta)).  Only the axial dipole
+ * (pole_lat_deg = 90) is implemented. */
+typedef struct {
+    double B0_tesla;
+    double pole_lat_deg, pole_lon_deg;
+} rt_dipole;
+
+/* A launch fan: every combination of frequency, mode, elevation and
+ * azimuth.  Ray index = ((i_freq * n_mode + i_mode) * n_elev + i_elev)
+ * * n_az + i_az, modes ordered O then X; n_mode = number of bits set in
+ * modes.  Elevation in [0, 90] above the horizon, azimuth clockwise from
+ * north.  The arrays are host memory, read during the call only. */
+typedef struct {
+    double tx_lat_deg, tx_lon_deg, tx_h_km;
+    const double *elev_deg;
+    int32_t n_elev;
+    int32_t n_az;
+    const double *az_deg;
+    const double *freq_mhz;
+    int32_t n_freq;
+    uint32_t modes;     /* RT_MODE_O | RT_MODE_X; both modes give the same
+                           isotropic ray when no field is set              */
+} rt_fan;
+
+typedef struct {
+    double step_km;         /* fixed RK4 step in group path, > 0           */
+    double max_group_km;    /* MAX_PATH limit, > 0                         */
+    double exit_h_km;       /* ESCAPE height; <= 0 means the grid top      */
+    int32_t precision;      /* RT_FP64, or RT_MIXED (FP32 interpolation and
+                               refractive index, FP64 integration)         */
+    int32_t traj_stride;    /* record every traj_stride-th step; 0 = none  */
+    int64_t traj_capacity;  /* records available in rt_results.traj        */
+    int32_t results_mem;    /* RT_MEM_HOST or RT_MEM_DEVICE                */
+    int32_t steps_per_launch; /* 0 = default; > 0 caps RK4 steps per kernel
+                                 launch (a tuning knob, results unchanged) */
+} rt_trace_opts;
+
+/* Per-ray outputs, arrays of N_r = rt_fan_count() elements, owned by the
+ * caller, in host or device memory per rt_trace_opts.results_mem.  Any
+ * pointer may be NULL to skip that output.
+ *   group_km    group path P' (includes the vacuum segments)
+ *   phase_km    phase path P = integral of n . dx
+ *   range_km    ground range R * (central angle transmitter -> landing)
+ *   az_dev_deg  initial great-circle bearing transmitter -> landing minus the
+ *               launch azimuth, in (-180, 180]; 0 when the range is ~0
+ *   apogee_km   largest height over the RK4 step ends (reflection height)
+ *   land_*_deg  landing point (GROUND) or the point under the last state
+ *   status      RT_RAY_*; NUMERIC rays have NaN outputs
+ *   n_steps     RK4 steps taken
+ * Trajectory (optional): ray i owns records [i*per_ray, (i+1)*per_ray) of
+ * traj, per_ray = traj_capacity / N_r; a record is 8 doubles
+ * (r_km, theta_rad, phi_rad, n_r, n_theta, n_phi, P'_km, P_km) taken at
+ * steps 0, stride, 2*stride, ... and at the last step; traj_count[i] is
+ * the number written (capped at per_ray, RT_W_TRAJ_TRUNCATED if any
+ * ray was capped). */
+typedef struct {
+    double *group_km, *phase_km, *range_km, *az_dev_deg, *apogee_km;
+    double *land_lat_deg, *land_lon_deg;
+    int32_t *status, *n_steps;
+    double *traj;
+    int32_t *traj_count;
+    int64_t total_steps;    /* out: sum of n_steps over the fan            */
+    double kernel_ms;       /* out: device time of the integration kernels */
+} rt_results;
+
+/* Create a context on HIP device `device` issuing work on `hip_stream`
+ * (a hipStream_t, borrowed; NULL = the null stream).  The context owns
+ * its device workspace.  RT_E_DEVICE if the device cannot be used. */
+rt_status rt_ctx_create(int32_t device, void *hip_stream, rt_ctx **out);
+void rt_ctx_destroy(rt_ctx *ctx);
+const char *rt_last_error(const rt_ctx *ctx);
+
+/* Upload a grid (preprocessing module of Sec. II-C).  `values` points to
+ * n_lat*n_lon*n_h elements of geom->dtype in host or device memory
+ * (values_mem); it is copied and converted (f_N^2 in MHz^2 for the FP64
+ * path and an FP32 copy for the mixed path), so the caller keeps its
+ * buffer.  RT_E_INVALID on a bad geometry or a negative / non-finite value;
+ * RT_E_NOMEM if the device copy cannot be allocated.  No field is set. */
+rt_status rt_grid_create(rt_ctx *ctx, const rt_grid_geom *geom, const void *values,
+                         int32_t values_mem, rt_grid **out);
+void rt_grid_destroy(rt_grid *grid);
+
+/* Set (or with d == NULL / B0 == 0 clear) the dipole field of a grid,
+ * stored by value.  RT_E_UNSUPPORTED for a tilted dipole. */
+rt_status rt_field_set(rt_grid *grid, const rt_dipole *d);
+
+/* Trace every ray of a fan through a grid (main processing module of
+ * Sec. II-C) and write the per-ray outputs.  Synchronous on the context's
+ * stream.  RT_E_INVALID on bad options or fan values; RT_E_UNSUPPORTED if
+ * a frequency is at or below the largest electron gyrofrequency of the
+ * field (Y >= 1), or the transmitter is not below the grid bottom.
+ * Per-ray failures are statuses, not call failures.  An empty fan is a
+ * no-op returning RT_OK. */
+rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                   const rt_trace_opts *opts, rt_results *res);
+
+/* Host-only helpers (no device needed). */
+rt_status rt_fan_count(const rt_fan *fan, int64_t *n_rays);
+rt_status rt_check_geom(const rt_grid_geom *geom);
+void rt_default_opts(rt_trace_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,299 @@
+"""Thin ctypes binding of librtgd (the HIP C-ABI declared in include/rtgd.h).
+
+Argument marshalling only: every step of the ray tracing runs in the HIP
+kernels of librtgd.so.  PyTorch is used, when results are requested on the
+device, for device memory and the current stream.  If the library has not
+been built, importing works but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtgd.so")
+
+RT_OK, RT_W_TRAJ_TRUNCATED = 0, 1
+RT_E_INVALID, RT_E_NOMEM, RT_E_DEVICE, RT_E_UNSUPPORTED = -1, -2, -3, -4
+RT_F64, RT_F32 = 0, 1
+RT_NE_M3, RT_FN2_MHZ2 = 0, 1
+RT_INTERP_GD, RT_INTERP_CR = 0, 1
+RT_MODE_O, RT_MODE_X = 1, 2
+RT_FP64, RT_MIXED = 0, 1
+RT_MEM_HOST, RT_MEM_DEVICE = 0, 1
+GROUND, ESCAPE, MAX_PATH, NUMERIC = 0, 1, 2, 3
+STATUS_NAMES = {RT_OK: "RT_OK", RT_W_TRAJ_TRUNCATED: "RT_W_TRAJ_TRUNCATED",
+                RT_E_INVALID: "RT_E_INVALID", RT_E_NOMEM: "RT_E_NOMEM",
+                RT_E_DEVICE: "RT_E_DEVICE", RT_E_UNSUPPORTED: "RT_E_UNSUPPORTED"}
+
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int32)
+
+
+class GridGeom(ctypes.Structure):
+    _fields_ = [("n_lat", ctypes.c_int32), ("n_lon", ctypes.c_int32), ("n_h", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("quantity", ctypes.c_int32),
+                ("interp", ctypes.c_int32),
+                ("lat0_deg", ctypes.c_double), ("dlat_deg", ctypes.c_double),
+                ("lon0_deg", ctypes.c_double), ("dlon_deg", ctypes.c_double),
+                ("h0_km", ctypes.c_double), ("dh_km", ctypes.c_double),
+                ("earth_radius_km", ctypes.c_double)]
+
+
+class Dipole(ctypes.Structure):
+    _fields_ = [("B0_tesla", ctypes.c_double), ("pole_lat_deg", ctypes.c_double),
+                ("pole_lon_deg", ctypes.c_double)]
+
+
+class Fan(ctypes.Structure):
+    _fields_ = [("tx_lat_deg", ctypes.c_double), ("tx_lon_deg", ctypes.c_double),
+                ("tx_h_km", ctypes.c_double),
+                ("elev_deg", _DP), ("n_elev", ctypes.c_int32), ("n_az", ctypes.c_int32),
+                ("az_deg", _DP), ("freq_mhz", _DP), ("n_freq", ctypes.c_int32),
+                ("modes", ctypes.c_uint32)]
+
+
+class TraceOpts(ctypes.Structure):
+    _fields_ = [("step_km", ctypes.c_double), ("max_group_km", ctypes.c_double),
+                ("exit_h_km", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("traj_stride", ctypes.c_int32), ("traj_capacity", ctypes.c_int64),
+                ("results_mem", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32)]
+
+
+class Results(ctypes.Structure):
+    _fields_ = [("group_km", _DP), ("phase_km", _DP), ("range_km", _DP),
+                ("az_dev_deg", _DP), ("apogee_km", _DP), ("land_lat_deg", _DP),
+                ("land_lon_deg", _DP), ("status", _IP), ("n_steps", _IP),
+                ("traj", _DP), ("traj_count", _IP), ("total_steps", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double)]
+
+
+OUT_DOUBLE = ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km",
+              "land_lat_deg", "land_lon_deg")
+OUT_INT = ("status", "n_steps")
+
+_lib = None
+
+
+class RTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load librtgd.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2506_18579_amd.build` (there is no CPU fallback)")
+    # PyTorch ships its own HIP runtime with the same soname as the system
+    # one; loading torch first makes librtgd bind to that single runtime
+    # instead of bringing a second copy into the process.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.rt_ctx_create.argtypes = [ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.rt_ctx_create.restype = ctypes.c_int32
+    L.rt_ctx_destroy.argtypes = [vp]
+    L.rt_ctx_destroy.restype = None
+    L.rt_last_error.argtypes = [vp]
+    L.rt_last_error.restype = ctypes.c_char_p
+    L.rt_grid_create.argtypes = [vp, ctypes.POINTER(GridGeom), vp, ctypes.c_int32,
+                                 ctypes.POINTER(vp)]
+    L.rt_grid_create.restype = ctypes.c_int32
+    L.rt_grid_destroy.argtypes = [vp]
+    L.rt_grid_destroy.restype = None
+    L.rt_field_set.argtypes = [vp, ctypes.POINTER(Dipole)]
+    L.rt_field_set.restype = ctypes.c_int32
+    L.rt_trace.argtypes = [vp, vp, ctypes.POINTER(Fan), ctypes.POINTER(TraceOpts),
+                           ctypes.POINTER(Results)]
+    L.rt_trace.restype = ctypes.c_int32
+    L.rt_fan_count.argtypes = [ctypes.POINTER(Fan), ctypes.POINTER(ctypes.c_int64)]
+    L.rt_fan_count.restype = ctypes.c_int32
+    L.rt_check_geom.argtypes = [ctypes.POINTER(GridGeom)]
+    L.rt_check_geom.restype = ctypes.c_int32
+    L.rt_default_opts.argtypes = [ctypes.POINTER(TraceOpts)]
+    L.rt_default_opts.restype = None
+    _lib = L
+    return L
+
+
+def make_geom(geom, dtype=RT_F64, quantity=RT_NE_M3, interp="gd") -> GridGeom:
+    g = GridGeom()
+    g.n_lat, g.n_lon, g.n_h = geom.n_lat, geom.n_lon, geom.n_h
+    g.dtype, g.quantity = dtype, quantity
+    g.interp = RT_INTERP_CR if interp == "cr" else RT_INTERP_GD
+    g.lat0_deg, g.dlat_deg = geom.lat0_deg, geom.dlat_deg
+    g.lon0_deg, g.dlon_deg = geom.lon0_deg, geom.dlon_deg
+    g.h0_km, g.dh_km = geom.h0_km, geom.dh_km
+    g.earth_radius_km = geom.earth_radius_km
+    return g
+
+
+class FanArgs:
+    """rt_fan with its arrays kept alive."""
+
+    def __init__(self, fan):
+        self.elev = np.ascontiguousarray(fan.elev_deg, dtype=np.float64)
+        self.az = np.ascontiguousarray(fan.az_deg, dtype=np.float64)
+        self.freq = np.ascontiguousarray(fan.freq_mhz, dtype=np.float64)
+        modes = 0
+        for m in fan.modes:
+            modes |= RT_MODE_O if m > 0 else RT_MODE_X
+        if list(fan.modes) not in ([1], [-1], [1, -1]):
+            raise ValueError("fan.modes must be (1,), (-1,) or (1, -1)")
+        self.s = Fan(fan.tx_lat_deg, fan.tx_lon_deg, fan.tx_h_km,
+                     self.elev.ctypes.data_as(_DP), self.elev.size, self.az.size,
+                     self.az.ctypes.data_as(_DP), self.freq.ctypes.data_as(_DP),
+                     self.freq.size, modes)
+
+
+def fan_count(fan) -> int:
+    fa = FanArgs(fan)
+    n = ctypes.c_int64(0)
+    st = lib().rt_fan_count(ctypes.byref(fa.s), ctypes.byref(n))
+    if st != RT_OK:
+        raise RTError(st, "invalid fan")
+    return int(n.value)
+
+
+def _torch_stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch  # device memory and streams come from PyTorch
+        if not torch.cuda.is_available():
+            raise RuntimeError("librtgd needs a ROCm GPU (torch.cuda.is_available() is False)")
+        torch.cuda.set_device(device)
+        self.device = device
+        if stream is None:
+            sptr = _torch_stream_ptr()
+        elif isinstance(stream, int):
+            sptr = ctypes.c_void_p(stream)
+        else:
+            sptr = ctypes.c_void_p(stream.cuda_stream)
+        self.h = ctypes.c_void_p()
+        st = lib().rt_ctx_create(device, sptr, ctypes.byref(self.h))
+        if st != RT_OK:
+            raise RTError(st, "rt_ctx_create failed: " + lib().rt_last_error(None).decode())
+
+    def error(self) -> str:
+        return lib().rt_last_error(self.h).decode()
+
+    def check(self, st, what):
+        if st not in (RT_OK, RT_W_TRAJ_TRUNCATED):
+            raise RTError(st, f"{what}: {self.error()}")
+        return st
+
+    def close(self):
+        if self.h:
+            lib().rt_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Grid:
+    """A grid resident on the device (rt_grid_create + rt_field_set)."""
+
+    def __init__(self, ctx: Context, grid, interp: str = "gd", values_f32_fn2=None):
+        self.ctx = ctx
+        if values_f32_fn2 is not None:
+            vals = np.ascontiguousarray(values_f32_fn2, dtype=np.float32)
+            g = make_geom(grid.geom, RT_F32, RT_FN2_MHZ2, interp)
+        else:
+            vals = np.ascontiguousarray(grid.values, dtype=np.float64)
+            g = make_geom(grid.geom, RT_F64, RT_NE_M3, interp)
+        self.geom = grid.geom
+        self.h = ctypes.c_void_p()
+        ctx.check(lib().rt_grid_create(ctx.h, ctypes.byref(g), vals.ctypes.data_as(ctypes.c_void_p),
+                                       RT_MEM_HOST, ctypes.byref(self.h)), "rt_grid_create")
+        self.set_field(grid.B0_T)
+
+    def set_field(self, B0_T: float):
+        d = Dipole(float(B0_T), 90.0, 0.0)
+        self.ctx.check(lib().rt_field_set(self.h, ctypes.byref(d)), "rt_field_set")
+        self.B0 = float(B0_T)
+
+    def close(self):
+        if self.h:
+            lib().rt_grid_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
+          precision="fp64", traj_stride=0, traj_per_ray=0, device_results=False, out=None):
+    """Trace every ray of `fan` (synth.Fan) through `grid`.
+
+    Returns a dict of per-ray arrays (numpy on the host, or torch tensors on
+    the device with device_results=True; pass `out` to reuse device
+    tensors), plus total_steps and kernel_ms."""
+    fa = FanArgs(fan)
+    n = ctypes.c_int64(0)
+    st = lib().rt_fan_count(ctypes.byref(fa.s), ctypes.byref(n))
+    if st != RT_OK:
+        raise RTError(st, "invalid fan")
+    n = int(n.value)
+    o = TraceOpts()
+    lib().rt_default_opts(ctypes.byref(o))
+    o.step_km, o.max_group_km, o.exit_h_km = step_km, max_group_km, exit_h_km
+    o.precision = RT_MIXED if precision == "mixed" else RT_FP64
+    o.traj_stride = traj_stride
+    o.traj_capacity = traj_per_ray * n if traj_stride > 0 else 0
+    o.results_mem = RT_MEM_DEVICE if device_results else RT_MEM_HOST
+    r = Results()
+    if device_results:
+        import torch
+        dev = torch.device("cuda", ctx.device)
+        if out is None:
+            out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in OUT_DOUBLE}
+            out.update({k: torch.empty(n, dtype=torch.int32, device=dev) for k in OUT_INT})
+            if traj_stride > 0:
+                out["traj"] = torch.empty((n, traj_per_ray, 8), dtype=torch.float64, device=dev)
+                out["traj_count"] = torch.empty(n, dtype=torch.int32, device=dev)
+        ptr = lambda t, P: ctypes.cast(ctypes.c_void_p(t.data_ptr()), P)
+    else:
+        out = {k: np.empty(n, dtype=np.float64) for k in OUT_DOUBLE}
+        out.update({k: np.empty(n, dtype=np.int32) for k in OUT_INT})
+        if traj_stride > 0:
+            out["traj"] = np.empty((n, traj_per_ray, 8), dtype=np.float64)
+            out["traj_count"] = np.empty(n, dtype=np.int32)
+        ptr = lambda a, P: a.ctypes.data_as(P)
+    for k in OUT_DOUBLE:
+        setattr(r, k, ptr(out[k], _DP))
+    for k in OUT_INT:
+        setattr(r, k, ptr(out[k], _IP))
+    if traj_stride > 0:
+        r.traj = ptr(out["traj"], _DP)
+        r.traj_count = ptr(out["traj_count"], _IP)
+    st = lib().rt_trace(ctx.h, grid.h, ctypes.byref(fa.s), ctypes.byref(o), ctypes.byref(r))
+    ctx.check(st, "rt_trace")
+    res = dict(out)
+    res["total_steps"] = int(r.total_steps)
+    res["kernel_ms"] = float(r.kernel_ms)
+    res["truncated"] = st == RT_W_TRAJ_TRUNCATED
+    return res
+
+
+def trace_raw(ctx: Context, grid: Grid, fan_struct: Fan, opts: TraceOpts, res: Results) -> int:
+    """Direct rt_trace call on prepared structs (returns the status)."""
+    return lib().rt_trace(ctx.h, grid.h, ctypes.byref(fan_struct), ctypes.byref(opts),
+                          ctypes.byref(res))

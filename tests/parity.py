@@ -1,0 +1,92 @@
+"""Parity helpers: compare GPU per-ray outputs with the FP64 oracle.
+
+Tolerances: FP64 path |gpu - oracle| <= 1e-9 * max(|oracle|, floor) with a
+floor of 1 km for lengths and 1 deg for angles, identical status and step
+count.  A ray that misses this is re-traced by the oracle at elevations
+beta (1 +- 1e-10); if that perturbation alone moves an output by more than
+1e-7 (relative, same floors) or flips its status, the ray is ill-conditioned
+(near the penetration boundary the outputs jump with beta): it then passes
+if it agrees to 1e-6 with one of the three oracle results (same status).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LEN_KEYS = ("group_km", "phase_km", "range_km", "apogee_km")
+ANG_KEYS = ("az_dev_deg", "land_lat_deg", "land_lon_deg")
+
+
+def _err(g, o, key):
+    floor = 1.0
+    return abs(g - o) / max(abs(o), floor)
+
+
+def ray_err(gpu, ora, i, j=None):
+    """Max scaled error over the float outputs of ray i (gpu) vs j (oracle)."""
+    j = i if j is None else j
+    if int(ora["status"][j]) == 3 and int(gpu["status"][i]) == 3:
+        return 0.0
+    return max(_err(float(gpu[k][i]), float(ora[k][j]), k) for k in LEN_KEYS + ANG_KEYS)
+
+
+def compare(gpu, ora, rays, trace_oracle, tol=1e-9, ill_tol=1e-6, gpu_idx=None):
+    """gpu: dict of host arrays (full fan); ora: oracle results for `rays`
+    (elev, az, freq, mode arrays of the sampled rays); gpu_idx maps sample
+    k -> gpu ray index.  trace_oracle(elev, az, freq, mode) re-traces rays.
+    Returns a report dict; raises AssertionError listing failures."""
+    elev, az, freq, mode = rays
+    n = elev.size
+    gpu_idx = np.arange(n) if gpu_idx is None else np.asarray(gpu_idx)
+    fails, ill, worst = [], [], 0.0
+    for k in range(n):
+        i = int(gpu_idx[k])
+        same_status = int(gpu["status"][i]) == int(ora["status"][k])
+        e = ray_err(gpu, ora, i, k) if same_status else np.inf
+        if same_status and e <= tol and int(gpu["n_steps"][i]) == int(ora["n_steps"][k]):
+            worst = max(worst, e)
+            continue
+        # conditioning probe
+        pe = np.array([elev[k] * (1 - 1e-10), elev[k] * (1 + 1e-10)])
+        pr = trace_oracle(pe, np.full(2, az[k]), np.full(2, freq[k]), np.full(2, mode[k]))
+        sens = 0.0
+        for m in range(2):
+            if int(pr["status"][m]) != int(ora["status"][k]):
+                sens = np.inf
+            else:
+                sens = max(sens, ray_err(pr, ora, m, k))
+        cands = [(ora, k)] + [(pr, m) for m in range(2)]
+        best = min((ray_err(gpu, c, i, j) if int(c["status"][j]) == int(gpu["status"][i])
+                    else np.inf) for c, j in cands)
+        if sens > 1e-7 and best <= ill_tol:
+            ill.append((i, float(elev[k]), float(freq[k]), int(mode[k]), float(best)))
+            continue
+        fails.append(dict(ray=i, elev=float(elev[k]), az=float(az[k]), freq=float(freq[k]),
+                          mode=int(mode[k]), gpu_status=int(gpu["status"][i]),
+                          ora_status=int(ora["status"][k]), err=float(e),
+                          gpu_steps=int(gpu["n_steps"][i]), ora_steps=int(ora["n_steps"][k]),
+                          sens=float(sens), best=float(best)))
+    report = dict(n=n, worst_rel=worst, ill_conditioned=ill, failures=fails)
+    assert not fails, f"{len(fails)} of {n} rays out of tolerance: {fails[:5]}"
+    return report
+
+
+def host(res):
+    """Torch device results -> numpy."""
+    out = {}
+    for k, v in res.items():
+        out[k] = v.cpu().numpy() if hasattr(v, "cpu") else v
+    return out
+
+
+def error_stats(gpu, ora, gpu_idx=None):
+    """Max and RMS absolute differences (km, km, km, deg) over rays with the
+    same status: group path, ground range, phase path, azimuth deviation."""
+    gpu_idx = np.arange(len(ora["status"])) if gpu_idx is None else np.asarray(gpu_idx)
+    same = np.asarray(gpu["status"])[gpu_idx] == np.asarray(ora["status"])
+    same &= np.asarray(ora["status"]) != 3
+    out = {"n_compared": int(same.sum()), "n_status_mismatch": int((~same).sum())}
+    for k in ("group_km", "range_km", "phase_km", "az_dev_deg", "apogee_km"):
+        d = np.asarray(gpu[k])[gpu_idx][same] - np.asarray(ora[k])[same]
+        out[k] = {"max": float(np.abs(d).max()) if d.size else 0.0,
+                  "rms": float(np.sqrt(np.mean(d ** 2))) if d.size else 0.0}
+    return out
