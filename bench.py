@@ -1,0 +1,174 @@
+"""Benchmark: ray-steps/s of batched GD ray tracing on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one rt_trace of the whole oblique-ionogram sweep (181x181x226
+anisotropic grid, 281 frequencies x 2 modes x 200 elevations = 112,400
+rays, FP64), grid and output buffers resident in HBM.  The same sweep is
+timed in mixed precision, the 24,576-ray anisotropic fan in both
+precisions, and fan latency percentiles are reported.  Accuracy is measured
+on a sample against the FP64 CPU oracle, which is also timed on the host
+cores as the CPU baseline.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP64 operations per RK4 step (4 right-hand sides + combine),
+# counted from the method (add/mul = 1, FMA = 2, div/sqrt/sincos = 1):
+# per RHS: cell location 13, 1-D GD weights 3 x 65, 4x4x4 contraction of
+# value + 3 partials 352 (+7 scaling), dipole 16, A-H setup 15, A-H partials
+# 42, Hamiltonian partials 50, ray equations 40 -> 730 (anisotropic);
+# isotropic RHS 617.  Per step 4 RHS + 136 (RK4 stages, termination).
+FLOPS_PER_STEP_ANISO = 4 * 730 + 136
+FLOPS_PER_STEP_ISO = 4 * 617 + 136
+PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (256 CU x 2.4 GHz x 128)
+PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample-stride", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup):
+    out = None
+    for _ in range(warmup):
+        out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
+                         exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out)
+    torch.cuda.synchronize()
+    walls, kms, total = [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
+                         exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out)
+        walls.append(time.perf_counter() - ts)
+        kms.append(out["kernel_ms"])
+        total += out["total_steps"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return dict(out=out, elapsed=elapsed, walls=walls, kernel_ms=kms, ray_steps=total)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: rays are independent and this build "
+              "measures the single-GPU shard (see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2506_18579_amd import rtgd, synth
+
+    ctx = rtgd.Context(0)
+    wl = synth.ionogram_workload(0)
+    grid = rtgd.Grid(ctx, wl.grid)
+
+    fp64 = time_trace(rtgd, torch, ctx, grid, wl, "fp64", a.steps, a.warmup)
+    mixed = time_trace(rtgd, torch, ctx, grid, wl, "mixed", max(1, a.steps), 1)
+    fan_wl = synth.aniso_fan_workload(0)
+    fan_grid = rtgd.Grid(ctx, fan_wl.grid)
+    fan64 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "fp64", max(3, a.steps), 1)
+    fan32 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "mixed", max(3, a.steps), 1)
+
+    steps_per_trace = fp64["ray_steps"] / a.steps
+    ms_per_step = fp64["elapsed"] / a.steps * 1e3
+    value = steps_per_trace / (ms_per_step / 1e3)
+    kms = float(np.mean(fp64["kernel_ms"]))
+    achieved = steps_per_trace * FLOPS_PER_STEP_ANISO / (kms * 1e-3) / 1e12
+
+    res64 = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in fp64["out"].items()}
+    res32 = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in mixed["out"].items()}
+
+    cpu = None
+    accuracy = {}
+    if not a.no_cpu:
+        from oracle import oracle as O
+        idx = np.arange(0, wl.fan.n_rays, a.cpu_sample_stride)
+        e, az, f, m = wl.fan.expand()
+        med = O.OracleMedium.from_grid(wl.grid)
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t = time.perf_counter()
+        o = O.trace(med, e[idx], az[idx], f[idx], m[idx], B0=wl.grid.B0_T,
+                    R=wl.grid.geom.earth_radius_km,
+                    tx=(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km),
+                    step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km,
+                    nthreads=nthreads)
+        dt = time.perf_counter() - t
+        cpu = {"value": o["total_steps"] / dt, "unit": "ray-steps/s", "cores": nthreads,
+               "kind": "oracle",
+               "sample": f"every {a.cpu_sample_stride}th ray of the 112,400-ray ionogram sweep "
+                         f"({idx.size} rays, {o['total_steps']} ray-steps, {dt:.1f} s, "
+                         f"plain FP64 C, OpenMP over rays)"}
+        same = (res64["status"][idx] == o["status"])
+        scale = lambda k, fl: np.abs(res64[k][idx][same] - o[k][same]) / np.maximum(np.abs(o[k][same]), fl)
+        rel = max(scale(k, 1.0).max() for k in ("group_km", "phase_km", "range_km", "az_dev_deg"))
+        accuracy["fp64_max_rel_vs_oracle"] = float(rel)
+        accuracy["fp64_status_mismatch"] = int((~same).sum())
+        same32 = (res32["status"][idx] == o["status"]) & (o["status"] != 3)
+        for k in ("group_km", "range_km", "az_dev_deg"):
+            d = res32[k][idx][same32] - o[k][same32]
+            accuracy[f"mixed_{k}_max"] = float(np.abs(d).max())
+            accuracy[f"mixed_{k}_rms"] = float(np.sqrt(np.mean(d * d)))
+        accuracy["mixed_status_mismatch"] = int((~same32 & (o["status"] != 3)).sum())
+        accuracy["sample_rays"] = int(idx.size)
+
+    lat = np.array(fan64["walls"]) * 1e3
+    lat32 = np.array(fan32["walls"]) * 1e3
+    line = {
+        "metric": "ray-steps/s at stated accuracy, FP64 vs mixed; p50/p99 ray-fan latency",
+        "value": value,
+        "unit": "ray-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "rays": wl.fan.n_rays, "grid": "181x181x226",
+                   "ray_steps_per_step": int(steps_per_trace), "field": "axial dipole 3.12e-5 T",
+                   "modes": "O+X", "step_km": wl.step_km, "exit_km": wl.exit_km,
+                   "max_group_km": wl.max_group_km},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+                     "traffic": None, "kernel": "k_trace<double>",
+                     "kernel_ms_avg": kms, "flops_per_ray_step": FLOPS_PER_STEP_ANISO},
+        "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "mixed": {"value": mixed["ray_steps"] / mixed["elapsed"],
+                  "kernel_ms_avg": float(np.mean(mixed["kernel_ms"])),
+                  "speedup_vs_fp64": (mixed["ray_steps"] / mixed["elapsed"]) / value},
+        "aniso_fan_24576": {
+            "fp64_ray_steps_per_s": fan64["ray_steps"] / fan64["elapsed"],
+            "mixed_ray_steps_per_s": fan32["ray_steps"] / fan32["elapsed"],
+            "fp64_latency_ms_p50": float(np.percentile(lat, 50)),
+            "fp64_latency_ms_p99": float(np.percentile(lat, 99)),
+            "mixed_latency_ms_p50": float(np.percentile(lat32, 50)),
+            "mixed_latency_ms_p99": float(np.percentile(lat32, 99))},
+    }
+    print(json.dumps(line), flush=True)
+    grid.close()
+    fan_grid.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,47 @@
+"""Small driver for rocprofv3 runs: optional plain device copy of a known
+size (calibrates the FETCH_SIZE / WRITE_SIZE counters), then `reps` traces
+of one workload.
+
+    python -m paper_2506_18579_amd.profile_run --workload ionogram --precision fp64 \
+        --reps 3 --copy-mb 256
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=("ionogram", "aniso", "iso"), default="ionogram")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--copy-mb", type=int, default=0)
+    a = ap.parse_args()
+    import torch
+    from paper_2506_18579_amd import rtgd, synth
+    if a.copy_mb:
+        n = a.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy {a.copy_mb} MiB read + {a.copy_mb} MiB write", flush=True)
+    wl = {"ionogram": lambda: synth.ionogram_workload(0),
+          "aniso": lambda: synth.aniso_fan_workload(0),
+          "iso": synth.iso_chapman_workload}[a.workload]()
+    ctx = rtgd.Context(0)
+    grid = rtgd.Grid(ctx, wl.grid)
+    out = None
+    for i in range(a.reps):
+        out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
+                         exit_h_km=wl.exit_km, precision=a.precision, device_results=True, out=out)
+        print(json.dumps({"rep": i, "workload": wl.name, "precision": a.precision,
+                          "ray_steps": out["total_steps"], "kernel_ms": out["kernel_ms"]}),
+              flush=True)
+    grid.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
