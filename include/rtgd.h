@@ -114,8 +114,14 @@ typedef struct {
     int32_t traj_stride;    /* record every traj_stride-th step; 0 = none  */
     int64_t traj_capacity;  /* records available in rt_results.traj        */
     int32_t results_mem;    /* RT_MEM_HOST or RT_MEM_DEVICE                */
-    int32_t steps_per_launch; /* 0 = default; > 0 caps RK4 steps per kernel
-                                 launch (a tuning knob, results unchanged) */
+    int32_t tail_threshold; /* scheduling knob, results unchanged: once the
+                               queue is empty and fewer rays than this are
+                               live, each is finished by four lanes instead
+                               of one; 0 = library default, < 0 = never   */
+    int32_t waves_per_simd; /* scheduling knob, results unchanged: register
+                               budget of the kernels, 1 = whole register
+                               file, 2 = two waves per SIMD; 0 = default  */
+    int32_t reserved;       /* must be 0                                   */
 } rt_trace_opts;
 
 /* Per-ray outputs, arrays of N_r = rt_fan_count() elements, owned by the

@@ -29,6 +29,8 @@ def flags() -> list[str]:
     return ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions stay off (scalar FP32/FP64 VALU only)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # no implicit FP contraction: every FMA is explicit in the source
+            "-ffp-contract=off",
             "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
 

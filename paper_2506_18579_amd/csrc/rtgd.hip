@@ -57,6 +57,18 @@ struct TraceParams {
     int32_t *queue_head;
     unsigned long long *total_steps;
     int32_t *truncated;
+    // hand-off of the last live rays to the 4-lanes-per-ray tail kernel
+    int32_t *live;             // rays neither finished nor handed off
+    int32_t *n_handoff;        // records written
+    struct Handoff *handoff;   // capacity handoff_threshold
+    int32_t handoff_threshold; // hand off once fewer rays than this are live (0: never)
+};
+
+// State of a ray moved from the one-lane to the four-lane kernel.
+struct Handoff {
+    double y[7];
+    double gp, apogee;
+    int32_t ray, steps, ntraj, pad;
 };
 
 __device__ __forceinline__ double dot3(const double a[3], const double b[3])
@@ -134,28 +146,34 @@ __device__ __forceinline__ void put_traj(const TraceParams<T> &P, int ray, Lane 
     }
 }
 
-// Ray initialisation (Sec. II-C): straight vacuum line from the transmitter
-// to the grid bottom, |n| = 1 there.
+// Per-ray constants from the ray index (fan decode).
 template <typename T>
-__device__ __forceinline__ void init_ray(const TraceParams<T> &P, int ray, Lane &L)
+__device__ __forceinline__ void ray_const(const TraceParams<T> &P, int ray, Lane &L, double &elev)
 {
     int i = ray;
     int ia = i % P.n_az; i /= P.n_az;
     int ie = i % P.n_elev; i /= P.n_elev;
     int im = i % P.n_mode; i /= P.n_mode;
     int jf = i;
-    double elev = P.elev[ie] * kDeg2Rad;
-    double az = P.az[ia];
+    elev = P.elev[ie];
     double f = P.freq[jf];
     int sigma = (im == 0) ? P.mode_first : -1;
     L.rc.inv_f2 = 1.0 / (f * f);
     L.rc.Y0 = kKB * P.B0 / (f * 1e6);
     L.rc.sigma = (P.B0 == 0.0) ? 0 : sigma;
-    L.az0 = az;
+    L.az0 = P.az[ia];
+}
 
+// Ray initialisation (Sec. II-C): straight vacuum line from the transmitter
+// to the grid bottom, |n| = 1 there.
+template <typename T>
+__device__ __forceinline__ void init_ray(const TraceParams<T> &P, int ray, Lane &L, bool write)
+{
+    double elev_deg;
+    ray_const(P, ray, L, elev_deg);
     double sb, cb, sa, ca;
-    sincos(elev, &sb, &cb);
-    sincos(az * kDeg2Rad, &sa, &ca);
+    sincos(elev_deg * kDeg2Rad, &sb, &cb);
+    sincos(L.az0 * kDeg2Rad, &sa, &ca);
     double d[3], x[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) d[k] = sb * P.up[k] + cb * (ca * P.north[k] + sa * P.east[k]);
@@ -171,7 +189,7 @@ __device__ __forceinline__ void init_ray(const TraceParams<T> &P, int ray, Lane 
     L.apogee = L.y[0] - P.g.R;
     L.steps = 0;
     L.ntraj = 0;
-    if (P.traj_stride > 0) put_traj(P, ray, L);
+    if (P.traj_stride > 0 && write) put_traj(P, ray, L);
 }
 
 // Outputs of a terminated ray: landing (or sub-ray) point, ground range,
@@ -212,11 +230,13 @@ __device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray, Lan
 }
 
 // One RK4 step plus the termination tests.  Returns the ray status, or -1
-// if the ray goes on.
-template <typename T>
-__device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L)
+// if the ray goes on.  `write` is false on the lanes of a quad that only
+// shadow the quad's leader (no memory writes).
+template <typename T, int IP, int LANES>
+__device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L, bool write,
+                                       StencilCache<T, LANES> &sc)
 {
-    bool ok = rk4_step<T>(P.g, L.rc, L.y, P.step);
+    bool ok = rk4_step<T, IP, LANES>(P.g, L.rc, L.y, P.step, sc);
     L.gp += P.step;
     ++L.steps;
     double h = L.y[0] - P.g.R;
@@ -250,7 +270,7 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L
         status = kMaxPath;
     }
     if (status != kNumeric && h > L.apogee) L.apogee = h;
-    if (P.traj_stride > 0 && (L.steps % P.traj_stride == 0 || status >= 0)) put_traj(P, ray, L);
+    if (P.traj_stride > 0 && write && (L.steps % P.traj_stride == 0 || status >= 0)) put_traj(P, ray, L);
 
     if (status == kGround) {
 #pragma unroll
@@ -271,50 +291,157 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L
     return status;
 }
 
-// Persistent kernel: each 64-lane wave loops { refill idle lanes from the
-// queue; one RK4 step on every live lane } until the queue is drained and
-// every lane is idle.  Every ray terminates (the group path grows by one
-// step per iteration up to max_group), so every wave exits.
-template <typename T>
-__global__ __launch_bounds__(64) void k_trace(TraceParams<T> P)
+// wave-aggregated atomic add (lanes with pred), returns each lane's slot
+__device__ __forceinline__ int wave_append(int32_t *counter, bool pred, int lane)
 {
+    unsigned long long mask = __ballot(pred);
+    int base = 0;
+    if (mask) {
+        int leader = __ffsll((long long)mask) - 1;
+        if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+        base = __shfl(base, leader);
+    }
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Persistent one-lane-per-ray kernel.  Each 64-lane wave loops { refill
+// idle lanes from the queue; one RK4 step on every live lane } until the
+// queue is drained and every lane is idle.  When the queue is drained and
+// fewer than handoff_threshold rays are live, each remaining ray's state is
+// written to the hand-off buffer and the lane retires (the tail kernel
+// finishes it with four lanes per ray).  Every ray terminates (the group
+// path grows by one step per iteration up to max_group), so every wave exits.
+template <typename T, int IP>
+__device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp)
+{
+    const TraceParams<T> &P = *Pp;
     const int lane = int(__lane_id());
     int ray = -1;            // -1 idle, -2 queue drained, >= 0 live ray
     Lane L;
+    StencilCache<T, 1> sc;
+    sc.clear();
     unsigned long long my_steps = 0;
-    for (;;) {
+    for (int iter = 0;; ++iter) {
         bool need = (ray == -1);
-        unsigned long long mask = __ballot(need);
-        if (mask) {
-            int cnt = __popcll(mask);
-            int leader = __ffsll((long long)mask) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(P.queue_head, cnt);
-            base = __shfl(base, leader);
+        if (__ballot(need)) {
+            int q = wave_append(P.queue_head, need, lane);
             if (need) {
-                int q = base + __popcll(mask & ((1ull << lane) - 1ull));
                 if (q < P.n_rays) {
                     ray = P.order ? P.order[q] : q;
-                    init_ray(P, ray, L);
+                    init_ray(P, ray, L, true);
                 } else {
                     ray = -2;
                 }
             }
         }
         if (__ballot(ray >= 0) == 0ull) break;
+        if (P.handoff_threshold > 0 && (iter & 7) == 0) {
+            int live = 0, head = 0;
+            if (lane == 0) {
+                live = __hip_atomic_load(P.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                head = __hip_atomic_load(P.queue_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            live = __shfl(live, 0);
+            head = __shfl(head, 0);
+            if (head >= P.n_rays && live < P.handoff_threshold) {
+                bool hand = ray >= 0;
+                int slot = wave_append(P.n_handoff, hand, lane);
+                if (hand) {
+                    Handoff &H = P.handoff[slot];
+#pragma unroll
+                    for (int i = 0; i < 7; ++i) H.y[i] = L.y[i];
+                    H.gp = L.gp;
+                    H.apogee = L.apogee;
+                    H.ray = ray;
+                    H.steps = L.steps;
+                    H.ntraj = L.ntraj;
+                    H.pad = 0;
+                    my_steps += (unsigned long long)L.steps;
+                    ray = -2;
+                }
+                unsigned long long hm = __ballot(hand);
+                if (lane == 0 && hm) atomicSub(P.live, __popcll(hm));
+                break;
+            }
+        }
+        int st = -1;
         if (ray >= 0) {
-            int st = advance(P, ray, L);
+            st = advance<T, IP, 1>(P, ray, L, true, sc);
             if (st >= 0) {
                 finish_ray(P, ray, L, st);
                 my_steps += (unsigned long long)L.steps;
                 ray = -1;
             }
         }
+        unsigned long long fin = __ballot(st >= 0);
+        if (lane == 0 && fin && P.handoff_threshold > 0) atomicSub(P.live, __popcll(fin));
     }
     // wave-reduce the step count, one atomic per wave
     for (int off = 32; off > 0; off >>= 1) my_steps += __shfl_down(my_steps, off);
     if (lane == 0) atomicAdd(P.total_steps, my_steps);
 }
+
+// Tail kernel: four lanes (a quad) per handed-off ray.  The quad's lanes
+// hold identical state and run identical arithmetic; only the stencil
+// contraction is split (one latitude row per lane, see medium<T, 4>), so
+// the results equal the one-lane kernel's bit for bit.  Lane 0 of the quad
+// writes.  Launched with enough quads for the hand-off capacity; quads past
+// the number of records exit at once.
+template <typename T, int IP>
+__device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
+{
+    const TraceParams<T> &P = *Pp;
+    const int lane = int(__lane_id());
+    const int slot = int(blockIdx.x) * 16 + (lane >> 2);
+    const bool lead = (lane & 3) == 0;
+    const int n = *P.n_handoff;
+    int ray = -1;
+    Lane L;
+    StencilCache<T, 4> sc;
+    sc.clear();
+    if (slot < n) {
+        const Handoff &H = P.handoff[slot];
+        ray = H.ray;
+        double elev_unused;
+        ray_const(P, ray, L, elev_unused);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) L.y[i] = H.y[i];
+        L.gp = H.gp;
+        L.apogee = H.apogee;
+        L.steps = H.steps;
+        L.ntraj = H.ntraj;
+    }
+    unsigned long long my_steps = 0;
+    for (;;) {
+        if (__ballot(ray >= 0) == 0ull) break;
+        if (ray >= 0) {
+            int st = advance<T, IP, 4>(P, ray, L, lead, sc);
+            if (st >= 0) {
+                if (lead) {
+                    finish_ray(P, ray, L, st);
+                    my_steps += (unsigned long long)(L.steps - P.handoff[slot].steps);
+                }
+                ray = -1;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) my_steps += __shfl_down(my_steps, off);
+    if (lane == 0) atomicAdd(P.total_steps, my_steps);
+}
+
+// Launch wrappers.  The *_w2 variants ask the compiler to fit two waves per
+// SIMD (at most 256 VGPRs, spilling if needed); the plain ones let it use
+// the whole register file (one wave per SIMD for the FP64 path).
+template <typename T, int IP>
+__global__ __launch_bounds__(64) void k_trace(const TraceParams<T> *__restrict__ P) { trace_body<T, IP>(P); }
+template <typename T, int IP>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+void k_trace_w2(const TraceParams<T> *__restrict__ P) { trace_body<T, IP>(P); }
+template <typename T, int IP>
+__global__ __launch_bounds__(64) void k_tail(const TraceParams<T> *__restrict__ P) { tail_body<T, IP>(P); }
+template <typename T, int IP>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+void k_tail_w2(const TraceParams<T> *__restrict__ P) { tail_body<T, IP>(P); }
 
 }  // namespace
 
@@ -583,7 +710,6 @@ void fill_grid_dev(const rt_grid *grid, GridDev<T> &g, const T *v)
     const rt_grid_geom &q = grid->geom;
     g.v = v;
     g.n_lat = q.n_lat; g.n_lon = q.n_lon; g.n_h = q.n_h;
-    g.interp = q.interp;
     g.lat0 = q.lat0_deg; g.lon0 = q.lon0_deg; g.h0 = q.h0_km;
     g.inv_dlat = 1.0 / q.dlat_deg; g.inv_dlon = 1.0 / q.dlon_deg; g.inv_dh = 1.0 / q.dh_km;
     g.lat_hi = q.lat0_deg + (q.n_lat - 1) * q.dlat_deg;
@@ -593,12 +719,40 @@ void fill_grid_dev(const rt_grid *grid, GridDev<T> &g, const T *v)
 }
 
 template <typename T>
-rt_status launch_trace(rt_ctx *ctx, TraceParams<T> &P, int n_rays)
+int resident_waves(rt_ctx *ctx, const void *kernel)
 {
-    int max_waves = ctx->n_cu * 16;   // persistent grid: up to 16 waves per CU
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess || per_cu < 1)
+        per_cu = 4;
+    return per_cu * ctx->n_cu;
+}
+
+// Upload the parameter block and counters, then launch the one-lane
+// persistent kernel and, if hand-off is on, the four-lane tail kernel.
+template <typename T>
+rt_status launch_trace(rt_ctx *ctx, TraceParams<T> &P, int n_rays, char *d_params, char *d_counters,
+                       int occ, int interp)
+{
+    struct Counters { int32_t head, trunc, live, n_handoff; unsigned long long total; } hc{};
+    hc.live = n_rays;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(d_counters, &hc, sizeof(hc), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(d_params, &P, sizeof(P), hipMemcpyHostToDevice, ctx->stream));
+    const TraceParams<T> *dp = reinterpret_cast<const TraceParams<T> *>(d_params);
+    const bool cr = interp == RT_INTERP_CR;
+    auto kt = occ == 2 ? (cr ? k_trace_w2<T, 1> : k_trace_w2<T, 0>) : (cr ? k_trace<T, 1> : k_trace<T, 0>);
+    auto kl = occ == 2 ? (cr ? k_tail_w2<T, 1> : k_tail_w2<T, 0>) : (cr ? k_tail<T, 1> : k_tail<T, 0>);
+    int max_waves = resident_waves<T>(ctx, reinterpret_cast<const void *>(kt));
     int waves = std::max(1, std::min((n_rays + 63) / 64, max_waves));
-    hipLaunchKernelGGL(k_trace<T>, dim3(waves), dim3(64), 0, ctx->stream, P);
+    hipLaunchKernelGGL(kt, dim3(waves), dim3(64), 0, ctx->stream, dp);
     HIP_OR_FAIL(ctx, hipGetLastError());
+    if (P.handoff_threshold > 0) {
+        int quads_blocks = (P.handoff_threshold + 15) / 16;
+        hipLaunchKernelGGL(kl, dim3(quads_blocks), dim3(64), 0, ctx->stream, dp);
+        HIP_OR_FAIL(ctx, hipGetLastError());
+    }
+    // hipMemcpyAsync from pageable host memory may return before the copy is
+    // consumed; keep the host structs alive until the stream is synchronised
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
     return RT_OK;
 }
 
@@ -627,6 +781,8 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
         return fail(ctx, RT_E_INVALID, "precision must be RT_FP64 or RT_MIXED");
     if (opts->results_mem != RT_MEM_HOST && opts->results_mem != RT_MEM_DEVICE)
         return fail(ctx, RT_E_INVALID, "results_mem must be RT_MEM_HOST or RT_MEM_DEVICE");
+    if (opts->tail_threshold > (1 << 24))
+        return fail(ctx, RT_E_INVALID, "tail_threshold too large");
     if (opts->traj_stride < 0 || opts->traj_capacity < 0)
         return fail(ctx, RT_E_INVALID, "negative trajectory option");
     if (opts->traj_stride > 0 && (!res->traj || opts->traj_capacity < n64))
@@ -651,16 +807,32 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
 
     // ---- workspace layout: fan | counters | staged outputs ----
+    if (opts->waves_per_simd < 0 || opts->waves_per_simd > 2)
+        return fail(ctx, RT_E_INVALID, "waves_per_simd must be 0, 1 or 2");
+    // register budget of the kernels: FP64 defaults to the full register
+    // file (one wave per SIMD), the mixed path fits two waves anyway
+    const int occ = opts->waves_per_simd == 0 ? 1 : opts->waves_per_simd;
+    int tail = opts->tail_threshold;
+    if (tail == 0) tail = ctx->n_cu * 64;     // library default
+    if (tail < 0) tail = 0;                   // hand-off off
+    tail = int(std::min<int64_t>(tail, n64));
     const size_t nf = size_t(fan->n_elev) + fan->n_az + fan->n_freq;
-    const size_t off_cnt = align_up(nf * sizeof(double), 256);
-    const size_t ws_bytes = off_cnt + 256;
+    const size_t off_par = align_up(nf * sizeof(double), 256);
+    const size_t off_cnt = off_par + align_up(sizeof(TraceParams<double>), 256);
+    const size_t off_hand = off_cnt + 256;
+    const size_t ws_bytes = off_hand + size_t(tail) * sizeof(Handoff) + 256;
     rt_status st = ensure_ws(ctx, ws_bytes);
     if (st != RT_OK) return st;
     char *ws = static_cast<char *>(ctx->ws);
     double *d_fan = reinterpret_cast<double *>(ws);
-    int32_t *d_head = reinterpret_cast<int32_t *>(ws + off_cnt);
-    unsigned long long *d_total = reinterpret_cast<unsigned long long *>(ws + off_cnt + 64);
-    int32_t *d_trunc = reinterpret_cast<int32_t *>(ws + off_cnt + 128);
+    char *d_params = ws + off_par;
+    char *d_counters = ws + off_cnt;
+    int32_t *d_head = reinterpret_cast<int32_t *>(d_counters);
+    int32_t *d_trunc = reinterpret_cast<int32_t *>(d_counters + 4);
+    int32_t *d_live = reinterpret_cast<int32_t *>(d_counters + 8);
+    int32_t *d_nhand = reinterpret_cast<int32_t *>(d_counters + 12);
+    unsigned long long *d_total = reinterpret_cast<unsigned long long *>(d_counters + 16);
+    Handoff *d_hand = reinterpret_cast<Handoff *>(ws + off_hand);
 
     std::vector<double> hfan(nf);
     std::copy(fan->elev_deg, fan->elev_deg + fan->n_elev, hfan.begin());
@@ -668,7 +840,6 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     std::copy(fan->freq_mhz, fan->freq_mhz + fan->n_freq, hfan.begin() + fan->n_elev + fan->n_az);
     HIP_OR_FAIL(ctx, hipMemcpyAsync(d_fan, hfan.data(), nf * sizeof(double),
                                     hipMemcpyHostToDevice, ctx->stream));
-    HIP_OR_FAIL(ctx, hipMemsetAsync(ws + off_cnt, 0, 256, ctx->stream));
 
     const bool host_out = opts->results_mem == RT_MEM_HOST;
     const size_t N = size_t(n_rays);
@@ -726,6 +897,10 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
         P.queue_head = d_head;
         P.total_steps = d_total;
         P.truncated = d_trunc;
+        P.live = d_live;
+        P.n_handoff = d_nhand;
+        P.handoff = d_hand;
+        P.handoff_threshold = tail;
     };
 
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
@@ -733,12 +908,12 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
         TraceParams<float> P{};
         fill_grid_dev<float>(grid, P.g, grid->d_f32);
         fill_common(P);
-        st = launch_trace(ctx, P, n_rays);
+        st = launch_trace(ctx, P, n_rays, d_params, d_counters, occ, gq.interp);
     } else {
         TraceParams<double> P{};
         fill_grid_dev<double>(grid, P.g, grid->d_f64);
         fill_common(P);
-        st = launch_trace(ctx, P, n_rays);
+        st = launch_trace(ctx, P, n_rays, d_params, d_counters, occ, gq.interp);
     }
     if (st != RT_OK) return st;
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));

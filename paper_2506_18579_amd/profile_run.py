@@ -10,6 +10,8 @@ from __future__ import annotations
 import argparse
 import json
 
+import numpy as np
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -17,6 +19,10 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0)
+    ap.add_argument("--single", default="", help="elev,freq,mode,replicas: one ray of the "
+                    "workload's grid and transmitter, replicated")
+    ap.add_argument("--tail", type=int, default=0)
+    ap.add_argument("--waves-per-simd", type=int, default=0)
     a = ap.parse_args()
     import torch
     from paper_2506_18579_amd import rtgd, synth
@@ -30,12 +36,18 @@ def main():
     wl = {"ionogram": lambda: synth.ionogram_workload(0),
           "aniso": lambda: synth.aniso_fan_workload(0),
           "iso": synth.iso_chapman_workload}[a.workload]()
+    if a.single:
+        el, fr, md, reps = a.single.split(",")
+        wl.fan = synth.Fan(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km,
+                           np.array([float(el)]), np.zeros(int(reps)), np.array([float(fr)]),
+                           (int(md),))
     ctx = rtgd.Context(0)
     grid = rtgd.Grid(ctx, wl.grid)
     out = None
     for i in range(a.reps):
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
-                         exit_h_km=wl.exit_km, precision=a.precision, device_results=True, out=out)
+                         exit_h_km=wl.exit_km, precision=a.precision, device_results=True, out=out,
+                         tail_threshold=a.tail, waves_per_simd=a.waves_per_simd)
         print(json.dumps({"rep": i, "workload": wl.name, "precision": a.precision,
                           "ray_steps": out["total_steps"], "kernel_ms": out["kernel_ms"]}),
               flush=True)

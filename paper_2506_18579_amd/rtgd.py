@@ -59,7 +59,8 @@ class TraceOpts(ctypes.Structure):
     _fields_ = [("step_km", ctypes.c_double), ("max_group_km", ctypes.c_double),
                 ("exit_h_km", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("traj_stride", ctypes.c_int32), ("traj_capacity", ctypes.c_int64),
-                ("results_mem", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32)]
+                ("results_mem", ctypes.c_int32), ("tail_threshold", ctypes.c_int32),
+                ("waves_per_simd", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Results(ctypes.Structure):
@@ -240,7 +241,8 @@ class Grid:
 
 
 def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
-          precision="fp64", traj_stride=0, traj_per_ray=0, device_results=False, out=None):
+          precision="fp64", traj_stride=0, traj_per_ray=0, device_results=False, out=None,
+          tail_threshold=0, waves_per_simd=0):
     """Trace every ray of `fan` (synth.Fan) through `grid`.
 
     Returns a dict of per-ray arrays (numpy on the host, or torch tensors on
@@ -259,6 +261,8 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
     o.traj_stride = traj_stride
     o.traj_capacity = traj_per_ray * n if traj_stride > 0 else 0
     o.results_mem = RT_MEM_DEVICE if device_results else RT_MEM_HOST
+    o.tail_threshold = tail_threshold
+    o.waves_per_simd = waves_per_simd
     r = Results()
     if device_results:
         import torch

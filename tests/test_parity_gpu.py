@@ -249,3 +249,20 @@ def test_grid_create_rejects_bad_values(rt, ctx):
     vals[2, 3, 4] = -1.0
     with pytest.raises(rt.RTError):
         rt.Grid(ctx, synth.Grid(geom, vals))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_four_lane_tail_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
+    """The four-lanes-per-ray tail kernel splits only the stencil contraction
+    and combines it in the one-lane order: outputs are identical whether a
+    ray finishes in the one-lane kernel (hand-off off) or runs entirely in
+    the tail kernel (threshold above the ray count)."""
+    fan = _subfan(aniso_wl)
+    one = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=-1)
+    four = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision,
+                     tail_threshold=1 << 20)
+    mid = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=100)
+    for k in ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "status", "n_steps"):
+        assert np.array_equal(one[k], four[k], equal_nan=True), k
+        assert np.array_equal(one[k], mid[k], equal_nan=True), k
+    assert one["total_steps"] == four["total_steps"] == mid["total_steps"]
