@@ -262,7 +262,25 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, double r, double th,
         sc.kh = kh;
     }
     __builtin_amdgcn_sched_barrier(0);
-    const T (&u)[ROWS][16] = sc.u;
+
+    // FP32 (mixed path): contract the differences u - u_ref to the cell's
+    // base node.  The weights sum to 1 and their derivatives to 0, so this is
+    // the same interpolant, but the gradient no longer cancels between large
+    // node values where the density varies little across the cell.
+    T u[ROWS][16];
+    T uref = T(0);
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (LANES == 1) {
+            uref = sc.u[1][4 * 1 + 1];               // node (a, b, c) = (1, 1, 1)
+        } else {
+            uref = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sc.u[0][4 * 1 + 1]),
+                                                              0x55, 0xF, 0xF, true));  // from lane a = 1
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) u[k][j] = sc.u[k][j] - uref;
 
     // IP = 0: Galerkin-Difference p = 3 (the method); IP = 1: Catmull-Rom
     T wo[4], dwo[4], wh[4], dwh[4];
@@ -314,7 +332,8 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, double r, double th,
     }
     // index space -> physical: t_h = (r - R - h0)/dh,
     // t_lat = (90 - theta deg - lat0)/dlat, t_lon = (phi deg - lon0)/dlon
-    F = v;
+    if constexpr (sizeof(T) == 4) F = v + uref;
+    else F = v;
     Fr = ch ? T(0) : gh * T(g.inv_dh);
     Fth = cl ? T(0) : glat * T(-kRad2Deg * g.inv_dlat);
     Fph = co ? T(0) : glon * T(kRad2Deg * g.inv_dlon);

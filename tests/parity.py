@@ -90,3 +90,24 @@ def error_stats(gpu, ora, gpu_idx=None):
         out[k] = {"max": float(np.abs(d).max()) if d.size else 0.0,
                   "rms": float(np.sqrt(np.mean(d ** 2))) if d.size else 0.0}
     return out
+
+
+def oracle_tracer(orc, wl, fan=None, **kw):
+    med = orc.OracleMedium.from_grid(wl.grid)
+    fan = fan or wl.fan
+    opts = dict(B0=wl.grid.B0_T, R=wl.grid.geom.earth_radius_km,
+                tx=(fan.tx_lat_deg, fan.tx_lon_deg, fan.tx_h_km), step=wl.step_km,
+                max_group=wl.max_group_km, exit_h=wl.exit_km)
+    opts.update(kw)
+
+    def tr(e, a, f, m, **extra):
+        o = dict(opts)
+        o.update(extra)
+        return orc.trace(med, e, a, f, m, **o)
+    return tr
+
+
+def gpu_trace(rt, ctx, grid, wl, fan=None, **kw):
+    args = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km)
+    args.update(kw)
+    return rt.trace(ctx, grid, fan or wl.fan, **args)

@@ -10,7 +10,7 @@ import pytest
 
 from paper_2506_18579_amd import synth
 
-from parity import compare, error_stats, host
+from parity import compare, error_stats, gpu_trace, host, oracle_tracer
 
 pytestmark = pytest.mark.gpu
 
@@ -51,27 +51,6 @@ def aniso_grid(rt, ctx, aniso_wl):
     g = rt.Grid(ctx, aniso_wl.grid)
     yield g
     g.close()
-
-
-def oracle_tracer(orc, wl, fan=None, **kw):
-    med = orc.OracleMedium.from_grid(wl.grid)
-    fan = fan or wl.fan
-    opts = dict(B0=wl.grid.B0_T, R=wl.grid.geom.earth_radius_km,
-                tx=(fan.tx_lat_deg, fan.tx_lon_deg, fan.tx_h_km), step=wl.step_km,
-                max_group=wl.max_group_km, exit_h=wl.exit_km)
-    opts.update(kw)
-
-    def tr(e, a, f, m, **extra):
-        o = dict(opts)
-        o.update(extra)
-        return orc.trace(med, e, a, f, m, **o)
-    return tr
-
-
-def gpu_trace(rt, ctx, grid, wl, fan=None, **kw):
-    args = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km)
-    args.update(kw)
-    return rt.trace(ctx, grid, fan or wl.fan, **args)
 
 
 def test_iso_chapman_every_ray(rt, ctx, orc, iso_wl, iso_grid):
