@@ -183,6 +183,79 @@ rt_status rt_field_set(rt_grid *grid, const rt_dipole *d);
 rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
                    const rt_trace_opts *opts, rt_results *res);
 
+/* Synthetic oblique ionogram from a traced frequency x elevation sweep
+ * (Sec. IV-B-4: joint frequency-elevation scanning).  `fan` is the fan that
+ * produced `res`: one azimuth (n_az == 1), elevations strictly increasing.
+ * For every (frequency, mode) trace and every pair of adjacent elevations
+ * whose rays both return to the ground with ground ranges on opposite sides
+ * of range_km (range - range_km changes sign, zero counting as positive),
+ * one received ray is reported, linearly interpolated in elevation:
+ * out[(t * max_points + k) * 4 + {0,1,2,3}] = elevation (deg), group path
+ * (km), phase path (km), apogee (km) of the k-th crossing of trace
+ * t = i_freq * n_mode + i_mode, in increasing elevation; counts[t] = number
+ * of crossings found (may exceed max_points; only max_points are written).
+ * res arrays group_km, phase_km, range_km, apogee_km and status are read;
+ * mem (RT_MEM_HOST / RT_MEM_DEVICE) says where res, out and counts live.
+ * RT_E_INVALID on a fan that is not a sweep or missing arrays. */
+rt_status rt_ionogram(rt_ctx *ctx, const rt_fan *fan, const rt_results *res, double range_km,
+                      int32_t max_points, int32_t mem, double *out, int32_t *counts);
+
+/* ------------------------------------------------------------------------
+ * Request server (continuous batching of ray-fan requests on one GPU).
+ *
+ * A server owns n_slots HIP streams (each with its own workspace and pinned
+ * staging) and a device-memory arena of mem_budget bytes for the outputs of
+ * admitted requests.  rt_server_submit copies the fan and never blocks: the
+ * request is launched at once if a slot is free and its outputs fit in the
+ * arena, otherwise it waits in a FIFO queue.  rt_server_poll launches
+ * queued requests as slots and memory free up and reports finished ones;
+ * requests in different slots run concurrently on the device.  A finished
+ * request keeps its outputs in the arena until rt_server_fetch copies them
+ * out and releases the memory.  Per-ray arithmetic does not depend on the
+ * slot or on what else runs, so a request's results are bit-identical alone
+ * and in a mix.  Grids stay resident (created with rt_grid_create on the
+ * same context) and may serve many requests.  Trajectories are not
+ * recorded by the server.  One host thread drives a server.
+ * ---------------------------------------------------------------------- */
+typedef struct rt_server rt_server;
+
+typedef struct {
+    int64_t mem_budget_bytes;  /* output arena; 0 = 256 MiB                  */
+    int32_t n_slots;           /* concurrent requests; 0 = 4                   */
+    int32_t reserved;          /* must be 0                                    */
+} rt_server_opts;
+
+typedef struct {
+    int64_t id;
+    int64_t n_rays;
+    int64_t total_steps;       /* RK4 steps of the request                     */
+    double kernel_ms;          /* device time of the request's kernels         */
+    rt_status status;          /* RT_OK or RT_W_TRAJ_TRUNCATED                 */
+    int32_t reserved;
+} rt_request_info;
+
+/* RT_E_NOMEM if the arena cannot be allocated. */
+rt_status rt_server_create(rt_ctx *ctx, const rt_server_opts *opts, rt_server **out);
+/* Waits for running requests, then frees everything the server owns. */
+void rt_server_destroy(rt_server *srv);
+/* opts->traj_stride must be 0 (RT_E_UNSUPPORTED otherwise); a request whose
+ * outputs exceed the whole arena is RT_E_NOMEM.  *id identifies it. */
+rt_status rt_server_submit(rt_server *srv, const rt_grid *grid, const rt_fan *fan,
+                           const rt_trace_opts *opts, int64_t *id);
+/* Non-blocking: launch what can be launched, then write up to `max` newly
+ * finished requests into done[] (*n_done of them). */
+rt_status rt_server_poll(rt_server *srv, rt_request_info *done, int32_t max, int32_t *n_done);
+/* Copy a finished request's per-ray outputs into res (arrays of n_rays,
+ * host or device memory per mem; NULL pointers skipped), release its arena
+ * memory and forget it.  RT_E_INVALID for an unknown or unfinished id. */
+rt_status rt_server_fetch(rt_server *srv, int64_t id, rt_results *res, int32_t mem);
+/* Drop a queued request (RT_OK) or mark a running one to be discarded when
+ * it finishes (RT_OK); RT_E_INVALID for an unknown id. */
+rt_status rt_server_cancel(rt_server *srv, int64_t id);
+/* Queue length, running requests, arena bytes in use. */
+rt_status rt_server_stats(const rt_server *srv, int32_t *queued, int32_t *running,
+                          int64_t *arena_used);
+
 /* Host-only helpers (no device needed). */
 rt_status rt_fan_count(const rt_fan *fan, int64_t *n_rays);
 rt_status rt_check_geom(const rt_grid_geom *geom);

@@ -238,3 +238,37 @@ def trace(med: OracleMedium, elev, az, freq, mode=None, B0=0.0, R=6371.0,
         res["traj"] = traj
         res["traj_count"] = tcount
     return res
+
+
+def ionogram(res, elev_deg, n_freq, n_mode, range_km, max_points=8):
+    """Oblique ionogram from a frequency x mode x elevation sweep (one
+    azimuth), following its definition: for each (frequency, mode) trace,
+    each adjacent elevation pair whose rays both reach the ground with
+    ground ranges on opposite sides of range_km (range - range_km changes
+    sign, zero counting as positive) gives one received ray, linearly
+    interpolated in elevation.  Returns (points[n_trace, max_points, 4] =
+    elevation, group, phase, apogee; counts[n_trace])."""
+    elev = np.asarray(elev_deg, dtype=np.float64)
+    n_elev = elev.size
+    n_trace = n_freq * n_mode
+    pts = np.zeros((n_trace, max_points, 4))
+    cnt = np.zeros(n_trace, dtype=np.int32)
+    for t in range(n_trace):
+        found = 0
+        for e in range(n_elev - 1):
+            i0 = t * n_elev + e
+            i1 = i0 + 1
+            if res["status"][i0] != GROUND or res["status"][i1] != GROUND:
+                continue
+            d0 = res["range_km"][i0] - range_km
+            d1 = res["range_km"][i1] - range_km
+            if (d0 < 0.0) == (d1 < 0.0):
+                continue
+            if found < max_points:
+                w = d0 / (d0 - d1)
+                pts[t, found, 0] = elev[e] + w * (elev[e + 1] - elev[e])
+                for j, k in ((1, "group_km"), (2, "phase_km"), (3, "apogee_km")):
+                    pts[t, found, j] = res[k][i0] + w * (res[k][i1] - res[k][i0])
+            found += 1
+        cnt[t] = found
+    return pts, cnt

@@ -14,6 +14,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
+#include <deque>
+#include <map>
+#include <unordered_map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -429,6 +433,39 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
     if (lane == 0) atomicAdd(P.total_steps, my_steps);
 }
 
+// Oblique-ionogram extraction: one thread per (frequency, mode) trace scans
+// its elevations for ground-range crossings of the receiver distance.
+__global__ __launch_bounds__(64) void k_ionogram(const double *__restrict__ elev, int n_elev,
+                                                 int n_trace, const double *__restrict__ group,
+                                                 const double *__restrict__ phase,
+                                                 const double *__restrict__ range,
+                                                 const double *__restrict__ apogee,
+                                                 const int32_t *__restrict__ status, double D,
+                                                 int max_points, double *__restrict__ out,
+                                                 int32_t *__restrict__ counts)
+{
+    int t = int(blockIdx.x) * 64 + int(threadIdx.x);
+    if (t >= n_trace) return;
+    int found = 0;
+    const size_t base = size_t(t) * size_t(n_elev);
+    for (int e = 0; e + 1 < n_elev; ++e) {
+        size_t i0 = base + e, i1 = i0 + 1;
+        if (status[i0] != kGround || status[i1] != kGround) continue;
+        double d0 = range[i0] - D, d1 = range[i1] - D;
+        if ((d0 < 0.0) == (d1 < 0.0)) continue;
+        if (found < max_points) {
+            double w = d0 / (d0 - d1);
+            double *o = out + (size_t(t) * size_t(max_points) + size_t(found)) * 4;
+            o[0] = fm(w, elev[e + 1] - elev[e], elev[e]);
+            o[1] = fm(w, group[i1] - group[i0], group[i0]);
+            o[2] = fm(w, phase[i1] - phase[i0], phase[i0]);
+            o[3] = fm(w, apogee[i1] - apogee[i0], apogee[i0]);
+        }
+        ++found;
+    }
+    counts[t] = found;
+}
+
 // Launch wrappers.  The *_w2 variants ask the compiler to fit two waves per
 // SIMD (at most 256 VGPRs, spilling if needed); the plain ones let it use
 // the whole register file (one wave per SIMD for the FP64 path).
@@ -458,6 +495,8 @@ struct rt_ctx {
     size_t ws_bytes = 0;
     void *stage = nullptr;      // result staging for host outputs
     size_t stage_bytes = 0;
+    void *pinned = nullptr;     // pinned host staging of fan, parameters, counters
+    size_t pinned_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -610,6 +649,7 @@ void rt_ctx_destroy(rt_ctx *c)
     (void)hipSetDevice(c->device);
     if (c->ws) (void)hipFree(c->ws);
     if (c->stage) (void)hipFree(c->stage);
+    if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -727,49 +767,38 @@ int resident_waves(rt_ctx *ctx, const void *kernel)
     return per_cu * ctx->n_cu;
 }
 
-// Upload the parameter block and counters, then launch the one-lane
-// persistent kernel and, if hand-off is on, the four-lane tail kernel.
-template <typename T>
-rt_status launch_trace(rt_ctx *ctx, TraceParams<T> &P, int n_rays, char *d_params, char *d_counters,
-                       int occ, int interp)
-{
-    struct Counters { int32_t head, trunc, live, n_handoff; unsigned long long total; } hc{};
-    hc.live = n_rays;
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(d_counters, &hc, sizeof(hc), hipMemcpyHostToDevice, ctx->stream));
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(d_params, &P, sizeof(P), hipMemcpyHostToDevice, ctx->stream));
-    const TraceParams<T> *dp = reinterpret_cast<const TraceParams<T> *>(d_params);
-    const bool cr = interp == RT_INTERP_CR;
-    auto kt = occ == 2 ? (cr ? k_trace_w2<T, 1> : k_trace_w2<T, 0>) : (cr ? k_trace<T, 1> : k_trace<T, 0>);
-    auto kl = occ == 2 ? (cr ? k_tail_w2<T, 1> : k_tail_w2<T, 0>) : (cr ? k_tail<T, 1> : k_tail<T, 0>);
-    int max_waves = resident_waves<T>(ctx, reinterpret_cast<const void *>(kt));
-    int waves = std::max(1, std::min((n_rays + 63) / 64, max_waves));
-    hipLaunchKernelGGL(kt, dim3(waves), dim3(64), 0, ctx->stream, dp);
-    HIP_OR_FAIL(ctx, hipGetLastError());
-    if (P.handoff_threshold > 0) {
-        int quads_blocks = (P.handoff_threshold + 15) / 16;
-        hipLaunchKernelGGL(kl, dim3(quads_blocks), dim3(64), 0, ctx->stream, dp);
-        HIP_OR_FAIL(ctx, hipGetLastError());
-    }
-    // hipMemcpyAsync from pageable host memory may return before the copy is
-    // consumed; keep the host structs alive until the stream is synchronised
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
-    return RT_OK;
-}
+// A validated trace request: the fan and options plus where its per-ray
+// outputs go on the device.
+struct TraceJob {
+    const rt_grid *grid = nullptr;
+    rt_fan fan{};
+    rt_trace_opts opts{};
+    int n_rays = 0;
+    int tail = 0;              // hand-off threshold actually used
+    int occ = 1;               // register budget variant
+    double *out[7] = {};       // group, phase, range, az_dev, apogee, land_lat, land_lon
+    int32_t *status = nullptr, *nsteps = nullptr, *tcount = nullptr;
+    double *traj = nullptr;
+    int64_t per_ray = 0;
+};
 
-}  // namespace
+static_assert(sizeof(TraceParams<float>) <= sizeof(TraceParams<double>),
+              "the workspace reserves room for the FP64 parameter block");
 
-extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
-                              const rt_trace_opts *opts, rt_results *res)
+// Counters the kernels update, read back after a trace.
+struct Counters {
+    int32_t head, trunc, live, n_handoff;
+    unsigned long long total;
+};
+
+// Check a request; on success fill job (except the output pointers).
+rt_status validate_job(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                       const rt_trace_opts *opts, TraceJob &job)
 {
-    if (!ctx) return RT_E_INVALID;
-    if (!grid || !fan || !opts || !res) return fail(ctx, RT_E_INVALID, "NULL argument");
+    if (!grid || !fan || !opts) return fail(ctx, RT_E_INVALID, "NULL argument");
     if (grid->ctx != ctx) return fail(ctx, RT_E_INVALID, "grid belongs to another context");
     int64_t n64 = 0;
     if (rt_fan_count(fan, &n64) != RT_OK) return fail(ctx, RT_E_INVALID, "invalid fan");
-    res->total_steps = 0;
-    res->kernel_ms = 0.0;
-    if (n64 == 0) return RT_OK;
-    const int n_rays = int(n64);
     const rt_grid_geom &gq = grid->geom;
     if (!(opts->step_km > 0) || !std::isfinite(opts->step_km))
         return fail(ctx, RT_E_INVALID, "step_km must be > 0");
@@ -783,10 +812,10 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
         return fail(ctx, RT_E_INVALID, "results_mem must be RT_MEM_HOST or RT_MEM_DEVICE");
     if (opts->tail_threshold > (1 << 24))
         return fail(ctx, RT_E_INVALID, "tail_threshold too large");
+    if (opts->waves_per_simd < 0 || opts->waves_per_simd > 2)
+        return fail(ctx, RT_E_INVALID, "waves_per_simd must be 0, 1 or 2");
     if (opts->traj_stride < 0 || opts->traj_capacity < 0)
         return fail(ctx, RT_E_INVALID, "negative trajectory option");
-    if (opts->traj_stride > 0 && (!res->traj || opts->traj_capacity < n64))
-        return fail(ctx, RT_E_INVALID, "trajectory needs traj and traj_capacity >= n_rays");
     if (!(fan->tx_h_km >= 0.0) || !(fan->tx_h_km < gq.h0_km))
         return fail(ctx, RT_E_UNSUPPORTED, "transmitter must lie below the grid bottom");
     if (!std::isfinite(fan->tx_lat_deg) || std::fabs(fan->tx_lat_deg) >= 90.0 ||
@@ -804,142 +833,609 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
         if (grid->B0 != 0.0 && f <= fH_max)
             return fail(ctx, RT_E_UNSUPPORTED, "frequency at or below the gyrofrequency (Y >= 1)");
     }
-    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-
-    // ---- workspace layout: fan | counters | staged outputs ----
-    if (opts->waves_per_simd < 0 || opts->waves_per_simd > 2)
-        return fail(ctx, RT_E_INVALID, "waves_per_simd must be 0, 1 or 2");
-    // register budget of the kernels: FP64 defaults to the full register
-    // file (one wave per SIMD), the mixed path fits two waves anyway
-    const int occ = opts->waves_per_simd == 0 ? 1 : opts->waves_per_simd;
+    job.grid = grid;
+    job.fan = *fan;
+    job.opts = *opts;
+    job.n_rays = int(n64);
+    job.occ = opts->waves_per_simd == 0 ? 1 : opts->waves_per_simd;
     int tail = opts->tail_threshold;
     if (tail == 0) tail = ctx->n_cu * 64;     // library default
     if (tail < 0) tail = 0;                   // hand-off off
-    tail = int(std::min<int64_t>(tail, n64));
-    const size_t nf = size_t(fan->n_elev) + fan->n_az + fan->n_freq;
-    const size_t off_par = align_up(nf * sizeof(double), 256);
+    job.tail = int(std::min<int64_t>(tail, n64));
+    job.per_ray = opts->traj_stride > 0 && n64 > 0 ? opts->traj_capacity / n64 : 0;
+    return RT_OK;
+}
+
+size_t fan_values(const rt_fan &f) { return size_t(f.n_elev) + f.n_az + f.n_freq; }
+
+// Device workspace: fan | parameter block | counters | hand-off buffer.
+size_t job_dev_bytes(const TraceJob &j)
+{
+    return align_up(fan_values(j.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256) + 256 +
+           size_t(j.tail) * sizeof(Handoff) + 256;
+}
+// Host staging (pinned when the caller provides it): fan | params | counters.
+size_t job_host_bytes(const TraceJob &j)
+{
+    return align_up(fan_values(j.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256) + 256;
+}
+
+template <typename T>
+void fill_params(const TraceJob &job, TraceParams<T> &P, const double *d_fan, char *d_counters,
+                 Handoff *d_hand)
+{
+    const rt_grid *grid = job.grid;
+    const rt_grid_geom &gq = grid->geom;
+    const rt_fan *fan = &job.fan;
+    const rt_trace_opts *opts = &job.opts;
+    fill_grid_dev<T>(grid, P.g, sizeof(T) == 4 ? reinterpret_cast<const T *>(grid->d_f32)
+                                                : reinterpret_cast<const T *>(grid->d_f64));
+    const double la = fan->tx_lat_deg * kDeg2Rad, lo = fan->tx_lon_deg * kDeg2Rad;
+    P.B0 = grid->B0;
+    P.elev = d_fan;
+    P.az = d_fan + fan->n_elev;
+    P.freq = d_fan + fan->n_elev + fan->n_az;
+    P.n_elev = fan->n_elev; P.n_az = fan->n_az; P.n_freq = fan->n_freq;
+    P.n_mode = popcount_modes(fan->modes);
+    P.mode_first = (fan->modes & RT_MODE_O) ? 1 : -1;
+    P.n_rays = job.n_rays;
+    P.tx_lon = lo;
+    P.up[0] = std::cos(la) * std::cos(lo); P.up[1] = std::cos(la) * std::sin(lo); P.up[2] = std::sin(la);
+    P.north[0] = -std::sin(la) * std::cos(lo); P.north[1] = -std::sin(la) * std::sin(lo);
+    P.north[2] = std::cos(la);
+    P.east[0] = -std::sin(lo); P.east[1] = std::cos(lo); P.east[2] = 0.0;
+    P.r0 = gq.earth_radius_km + fan->tx_h_km;
+    P.step = opts->step_km;
+    P.max_group = opts->max_group_km;
+    P.exit_h = opts->exit_h_km > 0 ? opts->exit_h_km : gq.h0_km + (gq.n_h - 1) * gq.dh_km;
+    P.floor_h = gq.h0_km;
+    P.max_steps = int32_t(std::ceil(opts->max_group_km / opts->step_km)) + 2;
+    P.traj_stride = opts->traj_stride;
+    P.traj_per_ray = job.per_ray;
+    P.group = job.out[0]; P.phase = job.out[1]; P.range = job.out[2]; P.azdev = job.out[3];
+    P.apogee = job.out[4]; P.land_lat = job.out[5]; P.land_lon = job.out[6];
+    P.status = job.status; P.nsteps = job.nsteps;
+    P.traj = job.traj; P.traj_count = job.tcount;
+    P.order = nullptr;
+    P.queue_head = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, head));
+    P.truncated = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, trunc));
+    P.live = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, live));
+    P.n_handoff = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, n_handoff));
+    P.total_steps = reinterpret_cast<unsigned long long *>(d_counters + offsetof(Counters, total));
+    P.handoff = d_hand;
+    P.handoff_threshold = job.tail;
+}
+
+// Enqueue one trace on `stream`: stage fan, parameter block and counters in
+// `host` (which must stay valid until the stream has consumed the copies),
+// copy them to `dev`, launch the one-lane persistent kernel and, with
+// hand-off on, the four-lane tail kernel; then copy the counters back into
+// host staging.  Events (optional) bracket the kernels.
+rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char *dev, char *host,
+                      hipEvent_t ev0, hipEvent_t ev1)
+{
+    const size_t nf = fan_values(job.fan);
+    const size_t off_par = align_up(nf * 8, 256);
     const size_t off_cnt = off_par + align_up(sizeof(TraceParams<double>), 256);
     const size_t off_hand = off_cnt + 256;
-    const size_t ws_bytes = off_hand + size_t(tail) * sizeof(Handoff) + 256;
-    rt_status st = ensure_ws(ctx, ws_bytes);
-    if (st != RT_OK) return st;
-    char *ws = static_cast<char *>(ctx->ws);
-    double *d_fan = reinterpret_cast<double *>(ws);
-    char *d_params = ws + off_par;
-    char *d_counters = ws + off_cnt;
-    int32_t *d_head = reinterpret_cast<int32_t *>(d_counters);
-    int32_t *d_trunc = reinterpret_cast<int32_t *>(d_counters + 4);
-    int32_t *d_live = reinterpret_cast<int32_t *>(d_counters + 8);
-    int32_t *d_nhand = reinterpret_cast<int32_t *>(d_counters + 12);
-    unsigned long long *d_total = reinterpret_cast<unsigned long long *>(d_counters + 16);
-    Handoff *d_hand = reinterpret_cast<Handoff *>(ws + off_hand);
+    double *h_fan = reinterpret_cast<double *>(host);
+    std::copy(job.fan.elev_deg, job.fan.elev_deg + job.fan.n_elev, h_fan);
+    std::copy(job.fan.az_deg, job.fan.az_deg + job.fan.n_az, h_fan + job.fan.n_elev);
+    std::copy(job.fan.freq_mhz, job.fan.freq_mhz + job.fan.n_freq, h_fan + job.fan.n_elev + job.fan.n_az);
+    Counters hc{};
+    hc.live = job.n_rays;
+    std::memcpy(host + off_cnt, &hc, sizeof(hc));
+    const double *d_fan = reinterpret_cast<const double *>(dev);
+    char *d_params = dev + off_par;
+    char *d_counters = dev + off_cnt;
+    Handoff *d_hand = reinterpret_cast<Handoff *>(dev + off_hand);
+    const bool cr = job.grid->geom.interp == RT_INTERP_CR;
+    const int occ = job.occ;
+    const void *kt;
+    const void *kl;
+    if (job.opts.precision == RT_MIXED) {
+        TraceParams<float> P{};
+        fill_params<float>(job, P, d_fan, d_counters, d_hand);
+        std::memcpy(host + off_par, &P, sizeof(P));
+        kt = occ == 2 ? (cr ? (const void *)k_trace_w2<float, 1> : (const void *)k_trace_w2<float, 0>)
+                      : (cr ? (const void *)k_trace<float, 1> : (const void *)k_trace<float, 0>);
+        kl = occ == 2 ? (cr ? (const void *)k_tail_w2<float, 1> : (const void *)k_tail_w2<float, 0>)
+                      : (cr ? (const void *)k_tail<float, 1> : (const void *)k_tail<float, 0>);
+    } else {
+        TraceParams<double> P{};
+        fill_params<double>(job, P, d_fan, d_counters, d_hand);
+        std::memcpy(host + off_par, &P, sizeof(P));
+        kt = occ == 2 ? (cr ? (const void *)k_trace_w2<double, 1> : (const void *)k_trace_w2<double, 0>)
+                      : (cr ? (const void *)k_trace<double, 1> : (const void *)k_trace<double, 0>);
+        kl = occ == 2 ? (cr ? (const void *)k_tail_w2<double, 1> : (const void *)k_tail_w2<double, 0>)
+                      : (cr ? (const void *)k_tail<double, 1> : (const void *)k_tail<double, 0>);
+    }
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(dev, host, off_hand, hipMemcpyHostToDevice, stream));
+    int max_waves = resident_waves<double>(ctx, kt);
+    int waves = std::max(1, std::min((job.n_rays + 63) / 64, max_waves));
+    void *arg = d_params;
+    void *args[] = {&arg};
+    if (ev0) HIP_OR_FAIL(ctx, hipEventRecord(ev0, stream));
+    HIP_OR_FAIL(ctx, hipLaunchKernel(kt, dim3(waves), dim3(64), args, 0, stream));
+    if (job.tail > 0)
+        HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 15) / 16), dim3(64), args, 0, stream));
+    if (ev1) HIP_OR_FAIL(ctx, hipEventRecord(ev1, stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(host + off_cnt, d_counters, sizeof(Counters),
+                                    hipMemcpyDeviceToHost, stream));
+    return RT_OK;
+}
 
-    std::vector<double> hfan(nf);
-    std::copy(fan->elev_deg, fan->elev_deg + fan->n_elev, hfan.begin());
-    std::copy(fan->az_deg, fan->az_deg + fan->n_az, hfan.begin() + fan->n_elev);
-    std::copy(fan->freq_mhz, fan->freq_mhz + fan->n_freq, hfan.begin() + fan->n_elev + fan->n_az);
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(d_fan, hfan.data(), nf * sizeof(double),
-                                    hipMemcpyHostToDevice, ctx->stream));
+rt_status ensure_pinned(rt_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->pinned_bytes) return RT_OK;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    size_t want = std::max(bytes, size_t(1) << 16);
+    HIP_OR_FAIL(ctx, hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    ctx->pinned_bytes = want;
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                              const rt_trace_opts *opts, rt_results *res)
+{
+    if (!ctx) return RT_E_INVALID;
+    if (!res) return fail(ctx, RT_E_INVALID, "NULL argument");
+    TraceJob job;
+    rt_status st = validate_job(ctx, grid, fan, opts, job);
+    if (st != RT_OK) return st;
+    res->total_steps = 0;
+    res->kernel_ms = 0.0;
+    if (job.n_rays == 0) return RT_OK;
+    const int64_t n64 = job.n_rays;
+    if (opts->traj_stride > 0 && (!res->traj || opts->traj_capacity < n64))
+        return fail(ctx, RT_E_INVALID, "trajectory needs traj and traj_capacity >= n_rays");
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    if ((st = ensure_ws(ctx, job_dev_bytes(job))) != RT_OK) return st;
+    if ((st = ensure_pinned(ctx, job_host_bytes(job))) != RT_OK) return st;
 
     const bool host_out = opts->results_mem == RT_MEM_HOST;
-    const size_t N = size_t(n_rays);
-    const int64_t per_ray = opts->traj_stride > 0 ? opts->traj_capacity / n64 : 0;
+    const size_t N = size_t(job.n_rays);
+    const int64_t per_ray = job.per_ray;
     double *dbl[7] = {res->group_km, res->phase_km, res->range_km, res->az_dev_deg,
                       res->apogee_km, res->land_lat_deg, res->land_lon_deg};
-    double *dev_dbl[7];
-    int32_t *dev_status = res->status, *dev_nsteps = res->n_steps, *dev_tcount = res->traj_count;
-    double *dev_traj = res->traj;
+    job.status = res->status;
+    job.nsteps = res->n_steps;
+    job.tcount = res->traj_count;
+    job.traj = per_ray > 0 ? res->traj : nullptr;
     if (host_out) {
         size_t bytes = 7 * N * 8 + 3 * N * 4 + 64;
         if (per_ray > 0) bytes = align_up(bytes, 256) + size_t(per_ray) * N * 64;
-        st = ensure_stage(ctx, bytes);
-        if (st != RT_OK) return st;
+        if ((st = ensure_stage(ctx, bytes)) != RT_OK) return st;
         char *sp = static_cast<char *>(ctx->stage);
-        for (int k = 0; k < 7; ++k) dev_dbl[k] = dbl[k] ? reinterpret_cast<double *>(sp + k * N * 8) : nullptr;
+        for (int k = 0; k < 7; ++k) job.out[k] = dbl[k] ? reinterpret_cast<double *>(sp + k * N * 8) : nullptr;
         char *ip = sp + 7 * N * 8;
-        dev_status = res->status ? reinterpret_cast<int32_t *>(ip) : nullptr;
-        dev_nsteps = res->n_steps ? reinterpret_cast<int32_t *>(ip + N * 4) : nullptr;
-        dev_tcount = res->traj_count ? reinterpret_cast<int32_t *>(ip + 2 * N * 4) : nullptr;
-        dev_traj = per_ray > 0 ? reinterpret_cast<double *>(sp + align_up(7 * N * 8 + 3 * N * 4 + 64, 256))
+        job.status = res->status ? reinterpret_cast<int32_t *>(ip) : nullptr;
+        job.nsteps = res->n_steps ? reinterpret_cast<int32_t *>(ip + N * 4) : nullptr;
+        job.tcount = res->traj_count ? reinterpret_cast<int32_t *>(ip + 2 * N * 4) : nullptr;
+        job.traj = per_ray > 0 ? reinterpret_cast<double *>(sp + align_up(7 * N * 8 + 3 * N * 4 + 64, 256))
                                : nullptr;
     } else {
-        for (int k = 0; k < 7; ++k) dev_dbl[k] = dbl[k];
+        for (int k = 0; k < 7; ++k) job.out[k] = dbl[k];
     }
-
-    const double la = fan->tx_lat_deg * kDeg2Rad, lo = fan->tx_lon_deg * kDeg2Rad;
-    auto fill_common = [&](auto &P) {
-        P.B0 = grid->B0;
-        P.elev = d_fan;
-        P.az = d_fan + fan->n_elev;
-        P.freq = d_fan + fan->n_elev + fan->n_az;
-        P.n_elev = fan->n_elev; P.n_az = fan->n_az; P.n_freq = fan->n_freq;
-        P.n_mode = popcount_modes(fan->modes);
-        P.mode_first = (fan->modes & RT_MODE_O) ? 1 : -1;
-        P.n_rays = n_rays;
-        P.tx_lon = lo;
-        P.up[0] = std::cos(la) * std::cos(lo); P.up[1] = std::cos(la) * std::sin(lo); P.up[2] = std::sin(la);
-        P.north[0] = -std::sin(la) * std::cos(lo); P.north[1] = -std::sin(la) * std::sin(lo);
-        P.north[2] = std::cos(la);
-        P.east[0] = -std::sin(lo); P.east[1] = std::cos(lo); P.east[2] = 0.0;
-        P.r0 = gq.earth_radius_km + fan->tx_h_km;
-        P.step = opts->step_km;
-        P.max_group = opts->max_group_km;
-        P.exit_h = opts->exit_h_km > 0 ? opts->exit_h_km : gq.h0_km + (gq.n_h - 1) * gq.dh_km;
-        P.floor_h = gq.h0_km;
-        P.max_steps = int32_t(std::ceil(opts->max_group_km / opts->step_km)) + 2;
-        P.traj_stride = opts->traj_stride;
-        P.traj_per_ray = per_ray;
-        P.group = dev_dbl[0]; P.phase = dev_dbl[1]; P.range = dev_dbl[2]; P.azdev = dev_dbl[3];
-        P.apogee = dev_dbl[4]; P.land_lat = dev_dbl[5]; P.land_lon = dev_dbl[6];
-        P.status = dev_status; P.nsteps = dev_nsteps;
-        P.traj = dev_traj; P.traj_count = dev_tcount;
-        P.order = nullptr;
-        P.queue_head = d_head;
-        P.total_steps = d_total;
-        P.truncated = d_trunc;
-        P.live = d_live;
-        P.n_handoff = d_nhand;
-        P.handoff = d_hand;
-        P.handoff_threshold = tail;
-    };
-
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    if (opts->precision == RT_MIXED) {
-        TraceParams<float> P{};
-        fill_grid_dev<float>(grid, P.g, grid->d_f32);
-        fill_common(P);
-        st = launch_trace(ctx, P, n_rays, d_params, d_counters, occ, gq.interp);
-    } else {
-        TraceParams<double> P{};
-        fill_grid_dev<double>(grid, P.g, grid->d_f64);
-        fill_common(P);
-        st = launch_trace(ctx, P, n_rays, d_params, d_counters, occ, gq.interp);
-    }
-    if (st != RT_OK) return st;
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-
-    unsigned long long total = 0;
-    int32_t trunc = 0;
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(&total, d_total, sizeof(total), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(&trunc, d_trunc, sizeof(trunc), hipMemcpyDeviceToHost, ctx->stream));
+    char *pinned = static_cast<char *>(ctx->pinned);
+    if ((st = enqueue_job(ctx, ctx->stream, job, static_cast<char *>(ctx->ws), pinned, ctx->ev0,
+                          ctx->ev1)) != RT_OK)
+        return st;
     if (host_out) {
         for (int k = 0; k < 7; ++k)
             if (dbl[k])
-                HIP_OR_FAIL(ctx, hipMemcpyAsync(dbl[k], dev_dbl[k], N * 8, hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(dbl[k], job.out[k], N * 8, hipMemcpyDeviceToHost, ctx->stream));
         if (res->status)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, dev_status, N * 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, job.status, N * 4, hipMemcpyDeviceToHost, ctx->stream));
         if (res->n_steps)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, dev_nsteps, N * 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, job.nsteps, N * 4, hipMemcpyDeviceToHost, ctx->stream));
         if (res->traj_count)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->traj_count, dev_tcount, N * 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->traj_count, job.tcount, N * 4, hipMemcpyDeviceToHost, ctx->stream));
         if (per_ray > 0)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->traj, dev_traj, size_t(per_ray) * N * 64,
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->traj, job.traj, size_t(per_ray) * N * 64,
                                             hipMemcpyDeviceToHost, ctx->stream));
     }
     HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.f;
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    res->total_steps = int64_t(total);
+    Counters hc;
+    const size_t off_cnt = align_up(fan_values(job.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256);
+    std::memcpy(&hc, pinned + off_cnt, sizeof(hc));
+    res->total_steps = int64_t(hc.total);
     res->kernel_ms = ms;
-    return trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+    return hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+}
+
+extern "C" rt_status rt_ionogram(rt_ctx *ctx, const rt_fan *fan, const rt_results *res,
+                                 double range_km, int32_t max_points, int32_t mem, double *out,
+                                 int32_t *counts)
+{
+    if (!ctx) return RT_E_INVALID;
+    if (!fan || !res || !out || !counts) return fail(ctx, RT_E_INVALID, "NULL argument");
+    if (fan->n_az != 1) return fail(ctx, RT_E_INVALID, "an ionogram sweep has one azimuth");
+    if (max_points < 1) return fail(ctx, RT_E_INVALID, "max_points must be >= 1");
+    if (!(range_km > 0.0) || !std::isfinite(range_km))
+        return fail(ctx, RT_E_INVALID, "range_km must be > 0");
+    if (mem != RT_MEM_HOST && mem != RT_MEM_DEVICE)
+        return fail(ctx, RT_E_INVALID, "mem must be RT_MEM_HOST or RT_MEM_DEVICE");
+    if (!res->group_km || !res->phase_km || !res->range_km || !res->apogee_km || !res->status)
+        return fail(ctx, RT_E_INVALID, "ionogram needs group, phase, range, apogee and status");
+    int64_t n64 = 0;
+    if (rt_fan_count(fan, &n64) != RT_OK) return fail(ctx, RT_E_INVALID, "invalid fan");
+    for (int i = 0; i + 1 < fan->n_elev; ++i)
+        if (!(fan->elev_deg[i + 1] > fan->elev_deg[i]))
+            return fail(ctx, RT_E_INVALID, "elevations must be strictly increasing");
+    const int n_trace = fan->n_freq * popcount_modes(fan->modes);
+    if (n64 == 0 || n_trace == 0) return RT_OK;
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    const size_t N = size_t(n64);
+    const size_t n_out = size_t(n_trace) * size_t(max_points) * 4;
+    // device staging: elev | group phase range apogee | status | out | counts
+    const size_t off_g = align_up(size_t(fan->n_elev) * 8, 256);
+    const size_t off_st = off_g + (mem == RT_MEM_HOST ? align_up(4 * N * 8, 256) : 0);
+    const size_t off_out = off_st + (mem == RT_MEM_HOST ? align_up(N * 4, 256) : 0);
+    const size_t off_cnt = off_out + (mem == RT_MEM_HOST ? align_up(n_out * 8, 256) : 0);
+    const size_t bytes = off_cnt + (mem == RT_MEM_HOST ? align_up(size_t(n_trace) * 4, 256) : 0) + 256;
+    rt_status st = ensure_stage(ctx, bytes);
+    if (st != RT_OK) return st;
+    char *sp = static_cast<char *>(ctx->stage);
+    double *d_elev = reinterpret_cast<double *>(sp);
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(d_elev, fan->elev_deg, size_t(fan->n_elev) * 8,
+                                    hipMemcpyHostToDevice, ctx->stream));
+    const double *g = res->group_km, *ph = res->phase_km, *rg = res->range_km, *ap = res->apogee_km;
+    const int32_t *stt = res->status;
+    double *d_out = out;
+    int32_t *d_cnt = counts;
+    if (mem == RT_MEM_HOST) {
+        double *dg = reinterpret_cast<double *>(sp + off_g);
+        const double *src[4] = {g, ph, rg, ap};
+        for (int k = 0; k < 4; ++k)
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(dg + k * N, src[k], N * 8, hipMemcpyHostToDevice, ctx->stream));
+        int32_t *ds = reinterpret_cast<int32_t *>(sp + off_st);
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ds, stt, N * 4, hipMemcpyHostToDevice, ctx->stream));
+        g = dg; ph = dg + N; rg = dg + 2 * N; ap = dg + 3 * N; stt = ds;
+        d_out = reinterpret_cast<double *>(sp + off_out);
+        d_cnt = reinterpret_cast<int32_t *>(sp + off_cnt);
+    }
+    hipLaunchKernelGGL(k_ionogram, dim3((n_trace + 63) / 64), dim3(64), 0, ctx->stream, d_elev,
+                       fan->n_elev, n_trace, g, ph, rg, ap, stt, range_km, max_points, d_out, d_cnt);
+    HIP_OR_FAIL(ctx, hipGetLastError());
+    if (mem == RT_MEM_HOST) {
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(out, d_out, n_out * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(counts, d_cnt, size_t(n_trace) * 4, hipMemcpyDeviceToHost,
+                                        ctx->stream));
+    }
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return RT_OK;
+}
+
+// ===========================================================================
+// Request server
+// ===========================================================================
+namespace {
+
+// Per-ray outputs of one request inside the arena: 7 doubles + 2 int32.
+constexpr size_t kOutBytesPerRay = 7 * 8 + 2 * 4;
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    char *dev = nullptr;
+    size_t dev_bytes = 0;
+    char *host = nullptr;          // pinned
+    size_t host_bytes = 0;
+    int64_t req = -1;              // running request, -1 idle
+};
+
+struct Request {
+    int64_t id = 0;
+    const rt_grid *grid = nullptr;
+    std::vector<double> elev, az, freq;
+    rt_fan fan{};
+    rt_trace_opts opts{};
+    TraceJob job;
+    size_t off = 0, bytes = 0;     // arena block
+    int state = 0;                 // 0 queued, 1 running, 2 done
+    bool cancelled = false;
+    rt_request_info info{};
+};
+
+// First-fit allocator over the arena (offsets, host bookkeeping only).
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    void init(char *b, size_t n) { base = b; size = n; free_.clear(); free_[0] = n; used = 0; }
+    bool alloc(size_t n, size_t &off)
+    {
+        n = align_up(std::max<size_t>(n, 256), 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                size_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                used += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = align_up(std::max<size_t>(n, 256), 256);
+        used -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+struct rt_server {
+    rt_ctx *ctx = nullptr;
+    std::vector<Slot> slots;
+    Arena arena;
+    std::deque<int64_t> queue;
+    std::unordered_map<int64_t, Request> reqs;
+    std::vector<rt_request_info> done;
+    int64_t next_id = 1;
+};
+
+namespace {
+
+rt_status slot_reserve(rt_ctx *ctx, Slot &sl, size_t dev_bytes, size_t host_bytes)
+{
+    if (dev_bytes > sl.dev_bytes) {
+        if (sl.dev) (void)hipFree(sl.dev);
+        sl.dev = nullptr;
+        sl.dev_bytes = 0;
+        HIP_OR_FAIL(ctx, hipMalloc(&sl.dev, dev_bytes));
+        sl.dev_bytes = dev_bytes;
+    }
+    if (host_bytes > sl.host_bytes) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.host_bytes = 0;
+        HIP_OR_FAIL(ctx, hipHostMalloc(&sl.host, host_bytes, hipHostMallocDefault));
+        sl.host_bytes = host_bytes;
+    }
+    return RT_OK;
+}
+
+// Launch queued requests in FIFO order while a slot is idle and the head
+// request's outputs fit in the arena.
+rt_status schedule(rt_server *srv)
+{
+    while (!srv->queue.empty()) {
+        int slot = -1;
+        for (size_t i = 0; i < srv->slots.size(); ++i)
+            if (srv->slots[i].req < 0) { slot = int(i); break; }
+        if (slot < 0) return RT_OK;
+        Request &r = srv->reqs[srv->queue.front()];
+        if (!srv->arena.alloc(r.bytes, r.off)) return RT_OK;   // wait for memory
+        srv->queue.pop_front();
+        Slot &sl = srv->slots[slot];
+        rt_status st = slot_reserve(srv->ctx, sl, job_dev_bytes(r.job), job_host_bytes(r.job));
+        if (st != RT_OK) return st;
+        const size_t N = size_t(r.job.n_rays);
+        char *b = srv->arena.base + r.off;
+        for (int k = 0; k < 7; ++k) r.job.out[k] = reinterpret_cast<double *>(b + k * N * 8);
+        r.job.status = reinterpret_cast<int32_t *>(b + 7 * N * 8);
+        r.job.nsteps = reinterpret_cast<int32_t *>(b + 7 * N * 8 + N * 4);
+        r.job.fan.elev_deg = r.elev.data();
+        r.job.fan.az_deg = r.az.data();
+        r.job.fan.freq_mhz = r.freq.data();
+        st = enqueue_job(srv->ctx, sl.stream, r.job, sl.dev, sl.host, sl.ev0, sl.ev1);
+        if (st != RT_OK) return st;
+        sl.req = r.id;
+        r.state = 1;
+    }
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" rt_status rt_server_create(rt_ctx *ctx, const rt_server_opts *opts, rt_server **out)
+{
+    if (!ctx || !out) return RT_E_INVALID;
+    *out = nullptr;
+    int64_t budget = opts && opts->mem_budget_bytes > 0 ? opts->mem_budget_bytes : (int64_t(256) << 20);
+    int n_slots = opts && opts->n_slots > 0 ? opts->n_slots : 4;
+    if (n_slots > 64) return fail(ctx, RT_E_INVALID, "at most 64 slots");
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    rt_server *srv = new (std::nothrow) rt_server();
+    if (!srv) return fail(ctx, RT_E_NOMEM, "host allocation failed");
+    srv->ctx = ctx;
+    char *base = nullptr;
+    hipError_t e = hipMalloc(&base, size_t(budget));
+    if (e != hipSuccess) {
+        delete srv;
+        return fail(ctx, RT_E_NOMEM, "server arena allocation failed");
+    }
+    srv->arena.init(base, size_t(budget));
+    srv->slots.resize(n_slots);
+    for (auto &sl : srv->slots) {
+        // default priority on purpose
+        if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess) {
+            rt_server_destroy(srv);
+            return fail(ctx, RT_E_DEVICE, std::string("server stream setup: ") + hipGetErrorString(e));
+        }
+    }
+    *out = srv;
+    return RT_OK;
+}
+
+extern "C" void rt_server_destroy(rt_server *srv)
+{
+    if (!srv) return;
+    (void)hipSetDevice(srv->ctx->device);
+    for (auto &sl : srv->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.ev0) (void)hipEventDestroy(sl.ev0);
+        if (sl.ev1) (void)hipEventDestroy(sl.ev1);
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.host) (void)hipHostFree(sl.host);
+    }
+    if (srv->arena.base) (void)hipFree(srv->arena.base);
+    delete srv;
+}
+
+extern "C" rt_status rt_server_submit(rt_server *srv, const rt_grid *grid, const rt_fan *fan,
+                                      const rt_trace_opts *opts, int64_t *id)
+{
+    if (!srv || !id) return RT_E_INVALID;
+    rt_ctx *ctx = srv->ctx;
+    if (opts && opts->traj_stride != 0)
+        return fail(ctx, RT_E_UNSUPPORTED, "the server does not record trajectories");
+    TraceJob job;
+    rt_status st = validate_job(ctx, grid, fan, opts, job);
+    if (st != RT_OK) return st;
+    Request r;
+    r.id = srv->next_id++;
+    r.grid = grid;
+    r.elev.assign(fan->elev_deg, fan->elev_deg + fan->n_elev);
+    r.az.assign(fan->az_deg, fan->az_deg + fan->n_az);
+    r.freq.assign(fan->freq_mhz, fan->freq_mhz + fan->n_freq);
+    r.job = job;
+    r.job.opts.results_mem = RT_MEM_DEVICE;
+    r.bytes = size_t(job.n_rays) * kOutBytesPerRay;
+    if (r.bytes > srv->arena.size) return fail(ctx, RT_E_NOMEM, "request larger than the arena");
+    r.info.id = r.id;
+    r.info.n_rays = job.n_rays;
+    *id = r.id;
+    if (job.n_rays == 0) {      // empty fan: done at once
+        r.state = 2;
+        r.info.status = RT_OK;
+        srv->done.push_back(r.info);
+        srv->reqs.emplace(r.id, std::move(r));
+        return RT_OK;
+    }
+    srv->reqs.emplace(r.id, std::move(r));
+    srv->queue.push_back(*id);
+    return schedule(srv);
+}
+
+extern "C" rt_status rt_server_poll(rt_server *srv, rt_request_info *done, int32_t max, int32_t *n_done)
+{
+    if (!srv || !n_done || (max > 0 && !done)) return RT_E_INVALID;
+    rt_ctx *ctx = srv->ctx;
+    *n_done = 0;
+    for (auto &sl : srv->slots) {
+        if (sl.req < 0) continue;
+        hipError_t e = hipEventQuery(sl.ev1);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return fail(ctx, RT_E_DEVICE, std::string("request: ") + hipGetErrorString(e));
+        // the counters copy follows ev1 on the stream
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(sl.stream));
+        Request &r = srv->reqs[sl.req];
+        Counters hc;
+        const size_t off_cnt = align_up(fan_values(r.job.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256);
+        std::memcpy(&hc, sl.host + off_cnt, sizeof(hc));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, sl.ev0, sl.ev1);
+        r.info.total_steps = int64_t(hc.total);
+        r.info.kernel_ms = ms;
+        r.info.status = hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+        r.state = 2;
+        sl.req = -1;
+        if (r.cancelled) {
+            srv->arena.release(r.off, r.bytes);
+            srv->reqs.erase(r.info.id);
+        } else {
+            srv->done.push_back(r.info);
+        }
+    }
+    rt_status st = schedule(srv);
+    if (st != RT_OK) return st;
+    int32_t k = 0;
+    while (k < max && !srv->done.empty()) {
+        done[k++] = srv->done.front();
+        srv->done.erase(srv->done.begin());
+    }
+    *n_done = k;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_server_fetch(rt_server *srv, int64_t id, rt_results *res, int32_t mem)
+{
+    if (!srv || !res) return RT_E_INVALID;
+    rt_ctx *ctx = srv->ctx;
+    auto it = srv->reqs.find(id);
+    if (it == srv->reqs.end() || it->second.state != 2)
+        return fail(ctx, RT_E_INVALID, "unknown or unfinished request");
+    if (mem != RT_MEM_HOST && mem != RT_MEM_DEVICE)
+        return fail(ctx, RT_E_INVALID, "mem must be RT_MEM_HOST or RT_MEM_DEVICE");
+    Request &r = it->second;
+    const size_t N = size_t(r.job.n_rays);
+    if (N > 0) {
+        hipMemcpyKind kind = mem == RT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        double *dst[7] = {res->group_km, res->phase_km, res->range_km, res->az_dev_deg,
+                          res->apogee_km, res->land_lat_deg, res->land_lon_deg};
+        for (int k = 0; k < 7; ++k)
+            if (dst[k]) HIP_OR_FAIL(ctx, hipMemcpyAsync(dst[k], r.job.out[k], N * 8, kind, ctx->stream));
+        if (res->status)
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, r.job.status, N * 4, kind, ctx->stream));
+        if (res->n_steps)
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, r.job.nsteps, N * 4, kind, ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        srv->arena.release(r.off, r.bytes);
+    }
+    res->total_steps = r.info.total_steps;
+    res->kernel_ms = r.info.kernel_ms;
+    srv->reqs.erase(it);
+    return schedule(srv);
+}
+
+extern "C" rt_status rt_server_cancel(rt_server *srv, int64_t id)
+{
+    if (!srv) return RT_E_INVALID;
+    auto it = srv->reqs.find(id);
+    if (it == srv->reqs.end()) return fail(srv->ctx, RT_E_INVALID, "unknown request");
+    Request &r = it->second;
+    if (r.state == 0) {
+        for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q)
+            if (*q == id) { srv->queue.erase(q); break; }
+        srv->reqs.erase(it);
+        return schedule(srv);
+    }
+    if (r.state == 1) {
+        r.cancelled = true;
+        return RT_OK;
+    }
+    // finished but not fetched: release now
+    for (auto d = srv->done.begin(); d != srv->done.end(); ++d)
+        if (d->id == id) { srv->done.erase(d); break; }
+    if (r.job.n_rays > 0) srv->arena.release(r.off, r.bytes);
+    srv->reqs.erase(it);
+    return schedule(srv);
+}
+
+extern "C" rt_status rt_server_stats(const rt_server *srv, int32_t *queued, int32_t *running,
+                                     int64_t *arena_used)
+{
+    if (!srv) return RT_E_INVALID;
+    int run = 0;
+    for (auto &sl : srv->slots) run += sl.req >= 0;
+    if (queued) *queued = int32_t(srv->queue.size());
+    if (running) *running = run;
+    if (arena_used) *arena_used = int64_t(srv->arena.used);
+    return RT_OK;
 }

@@ -71,6 +71,17 @@ class Results(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("n_slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("n_rays", ctypes.c_int64),
+                ("total_steps", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 OUT_DOUBLE = ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km",
               "land_lat_deg", "land_lon_deg")
 OUT_INT = ("status", "n_steps")
@@ -120,6 +131,26 @@ def lib():
     L.rt_check_geom.restype = ctypes.c_int32
     L.rt_default_opts.argtypes = [ctypes.POINTER(TraceOpts)]
     L.rt_default_opts.restype = None
+    L.rt_ionogram.argtypes = [vp, ctypes.POINTER(Fan), ctypes.POINTER(Results), ctypes.c_double,
+                              ctypes.c_int32, ctypes.c_int32, vp, vp]
+    L.rt_ionogram.restype = ctypes.c_int32
+    L.rt_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.rt_server_create.restype = ctypes.c_int32
+    L.rt_server_destroy.argtypes = [vp]
+    L.rt_server_destroy.restype = None
+    L.rt_server_submit.argtypes = [vp, vp, ctypes.POINTER(Fan), ctypes.POINTER(TraceOpts),
+                                   ctypes.POINTER(ctypes.c_int64)]
+    L.rt_server_submit.restype = ctypes.c_int32
+    L.rt_server_poll.argtypes = [vp, ctypes.POINTER(RequestInfo), ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32)]
+    L.rt_server_poll.restype = ctypes.c_int32
+    L.rt_server_fetch.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(Results), ctypes.c_int32]
+    L.rt_server_fetch.restype = ctypes.c_int32
+    L.rt_server_cancel.argtypes = [vp, ctypes.c_int64]
+    L.rt_server_cancel.restype = ctypes.c_int32
+    L.rt_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int64)]
+    L.rt_server_stats.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -240,6 +271,17 @@ class Grid:
             pass
 
 
+def make_opts(step_km=1.0, max_group_km=4000.0, exit_h_km=0.0, precision="fp64",
+              tail_threshold=0, waves_per_simd=0) -> TraceOpts:
+    o = TraceOpts()
+    lib().rt_default_opts(ctypes.byref(o))
+    o.step_km, o.max_group_km, o.exit_h_km = step_km, max_group_km, exit_h_km
+    o.precision = RT_MIXED if precision == "mixed" else RT_FP64
+    o.tail_threshold = tail_threshold
+    o.waves_per_simd = waves_per_simd
+    return o
+
+
 def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
           precision="fp64", traj_stride=0, traj_per_ray=0, device_results=False, out=None,
           tail_threshold=0, waves_per_simd=0):
@@ -254,15 +296,10 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
     if st != RT_OK:
         raise RTError(st, "invalid fan")
     n = int(n.value)
-    o = TraceOpts()
-    lib().rt_default_opts(ctypes.byref(o))
-    o.step_km, o.max_group_km, o.exit_h_km = step_km, max_group_km, exit_h_km
-    o.precision = RT_MIXED if precision == "mixed" else RT_FP64
+    o = make_opts(step_km, max_group_km, exit_h_km, precision, tail_threshold, waves_per_simd)
     o.traj_stride = traj_stride
     o.traj_capacity = traj_per_ray * n if traj_stride > 0 else 0
     o.results_mem = RT_MEM_DEVICE if device_results else RT_MEM_HOST
-    o.tail_threshold = tail_threshold
-    o.waves_per_simd = waves_per_simd
     r = Results()
     if device_results:
         import torch
@@ -301,3 +338,114 @@ def trace_raw(ctx: Context, grid: Grid, fan_struct: Fan, opts: TraceOpts, res: R
     """Direct rt_trace call on prepared structs (returns the status)."""
     return lib().rt_trace(ctx.h, grid.h, ctypes.byref(fan_struct), ctypes.byref(opts),
                           ctypes.byref(res))
+
+
+def ionogram(ctx: Context, fan, res, range_km: float, max_points: int = 8):
+    """Synthetic oblique ionogram (rt_ionogram) from the per-ray results of a
+    frequency x elevation sweep `fan` (one azimuth).  `res` is the dict
+    returned by trace() (numpy on the host or torch on the device).  Returns
+    (points[n_trace, max_points, 4] = elevation, group, phase, apogee;
+    counts[n_trace]) with trace t = i_freq * n_mode + i_mode."""
+    fa = FanArgs(fan)
+    n_trace = len(fan.freq_mhz) * len(fan.modes)
+    r = Results()
+    on_device = hasattr(res["group_km"], "data_ptr")
+    if on_device:
+        import torch
+        dev = res["group_km"].device
+        pts = torch.zeros((n_trace, max_points, 4), dtype=torch.float64, device=dev)
+        cnt = torch.zeros(n_trace, dtype=torch.int32, device=dev)
+        ptr = lambda t, P: ctypes.cast(ctypes.c_void_p(t.data_ptr()), P)
+        vptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    else:
+        pts = np.zeros((n_trace, max_points, 4), dtype=np.float64)
+        cnt = np.zeros(n_trace, dtype=np.int32)
+        ptr = lambda a, P: np.ascontiguousarray(a).ctypes.data_as(P)
+        vptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    keep = {k: (res[k] if on_device else np.ascontiguousarray(res[k]))
+            for k in ("group_km", "phase_km", "range_km", "apogee_km", "status")}
+    r.group_km = ptr(keep["group_km"], _DP)
+    r.phase_km = ptr(keep["phase_km"], _DP)
+    r.range_km = ptr(keep["range_km"], _DP)
+    r.apogee_km = ptr(keep["apogee_km"], _DP)
+    r.status = ptr(keep["status"], _IP)
+    st = lib().rt_ionogram(ctx.h, ctypes.byref(fa.s), ctypes.byref(r), float(range_km),
+                           int(max_points), RT_MEM_DEVICE if on_device else RT_MEM_HOST,
+                           vptr(pts), vptr(cnt))
+    ctx.check(st, "rt_ionogram")
+    return pts, cnt
+
+
+class Server:
+    """Request server (rt_server_*): continuous batching of ray-fan
+    requests over `n_slots` streams with a device output arena of
+    `mem_budget_bytes`.  submit() never blocks; poll() launches queued work
+    and returns finished requests; fetch() copies a finished request's
+    per-ray outputs out and frees its arena block."""
+
+    def __init__(self, ctx: Context, n_slots: int = 4, mem_budget_bytes: int = 256 << 20):
+        self.ctx = ctx
+        self.h = ctypes.c_void_p()
+        so = ServerOpts(int(mem_budget_bytes), int(n_slots), 0)
+        ctx.check(lib().rt_server_create(ctx.h, ctypes.byref(so), ctypes.byref(self.h)),
+                  "rt_server_create")
+        self._n = {}
+        self._buf = (RequestInfo * 64)()
+
+    def submit(self, grid: Grid, fan, **opts) -> int:
+        fa = FanArgs(fan)
+        o = make_opts(**opts)
+        rid = ctypes.c_int64(0)
+        self.ctx.check(lib().rt_server_submit(self.h, grid.h, ctypes.byref(fa.s), ctypes.byref(o),
+                                              ctypes.byref(rid)), "rt_server_submit")
+        return int(rid.value)
+
+    def poll(self) -> list:
+        """Finished requests since the last poll: dicts with id, n_rays,
+        total_steps, kernel_ms, status."""
+        out = []
+        while True:
+            n = ctypes.c_int32(0)
+            self.ctx.check(lib().rt_server_poll(self.h, self._buf, len(self._buf), ctypes.byref(n)),
+                           "rt_server_poll")
+            for i in range(n.value):
+                b = self._buf[i]
+                out.append(dict(id=int(b.id), n_rays=int(b.n_rays), total_steps=int(b.total_steps),
+                                kernel_ms=float(b.kernel_ms), status=int(b.status)))
+            if n.value < len(self._buf):
+                return out
+
+    def fetch(self, rid: int, n_rays: int) -> dict:
+        """Per-ray outputs of a finished request (numpy, host)."""
+        out = {k: np.empty(n_rays, dtype=np.float64) for k in OUT_DOUBLE}
+        out.update({k: np.empty(n_rays, dtype=np.int32) for k in OUT_INT})
+        r = Results()
+        for k in OUT_DOUBLE:
+            setattr(r, k, out[k].ctypes.data_as(_DP))
+        for k in OUT_INT:
+            setattr(r, k, out[k].ctypes.data_as(_IP))
+        self.ctx.check(lib().rt_server_fetch(self.h, int(rid), ctypes.byref(r), RT_MEM_HOST),
+                       "rt_server_fetch")
+        out["total_steps"] = int(r.total_steps)
+        out["kernel_ms"] = float(r.kernel_ms)
+        return out
+
+    def cancel(self, rid: int):
+        self.ctx.check(lib().rt_server_cancel(self.h, int(rid)), "rt_server_cancel")
+
+    def stats(self):
+        q, r, a = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int64(0)
+        self.ctx.check(lib().rt_server_stats(self.h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(a)),
+                       "rt_server_stats")
+        return dict(queued=q.value, running=r.value, arena_used=a.value)
+
+    def close(self):
+        if self.h:
+            lib().rt_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

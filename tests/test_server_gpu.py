@@ -1,0 +1,149 @@
+"""Request server (continuous batching) on the GPU.
+
+A Poisson stream of uneven ray fans against resident grid snapshots is
+pushed through rt_server_* with several slots, so that requests overlap on
+the device and later ones are admitted as slots and arena memory free up.
+Every request's per-ray outputs must equal, bit for bit, those of the same
+fan traced alone with rt_trace (the per-ray arithmetic does not depend on
+what else runs).  Admission by memory, cancellation and the error paths are
+checked too.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2506_18579_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "land_lat_deg",
+        "land_lon_deg", "status", "n_steps")
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2506_18579_amd import rtgd
+    rtgd.lib()
+    return rtgd
+
+
+@pytest.fixture(scope="module")
+def ctx(rt):
+    c = rt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def grids(rt, ctx):
+    gs = [rt.Grid(ctx, synth.ionosphere_grid(synth.GEOM_ANISO, seed)) for seed in (0, 1)]
+    yield gs
+    for g in gs:
+        g.close()
+
+
+def opts(precision):
+    return dict(step_km=1.0, max_group_km=4000.0, exit_h_km=600.0, precision=precision)
+
+
+def drain(srv, want, timeout_s=60.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < want:
+        for d in srv.poll():
+            done[d["id"]] = d
+        assert time.time() - t0 < timeout_s, f"server stalled: {srv.stats()}"
+        time.sleep(0.0005)
+    return done
+
+
+def same(a, b):
+    for k in KEYS:
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k]), equal_nan=True), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_each_result_same_alone_and_in_mix(rt, ctx, grids, precision):
+    reqs = synth.serving_requests(24, seed=7, n_snapshots=len(grids), max_rays=3000, qps=1e9)
+    srv = rt.Server(ctx, n_slots=4, mem_budget_bytes=64 << 20)
+    try:
+        ids = {}
+        peak_running = 0
+        for r in reqs:
+            ids[srv.submit(grids[r["snapshot"]], r["fan"], **opts(precision))] = r
+            peak_running = max(peak_running, srv.stats()["running"])
+        done = drain(srv, len(reqs))
+        assert peak_running >= 2          # work overlapped on the device
+        mixed = {rid: srv.fetch(rid, done[rid]["n_rays"]) for rid in ids}
+        st = srv.stats()
+        assert st == dict(queued=0, running=0, arena_used=0)
+    finally:
+        srv.close()
+    for rid, r in ids.items():
+        alone = rt.trace(ctx, grids[r["snapshot"]], r["fan"], **opts(precision))
+        assert done[rid]["n_rays"] == alone["status"].size
+        assert done[rid]["total_steps"] == alone["total_steps"]
+        same(mixed[rid], alone)
+
+
+def test_admission_by_memory(rt, ctx, grids):
+    """An arena that holds one request at a time: all requests still finish,
+    in submission order, with the same results."""
+    wl = synth.aniso_fan_workload(0)
+    fans = [synth.sub_fan(wl.fan, elev_idx=list(range(k, 64, 8)), az_idx=list(range(0, 64, 4)))
+            for k in range(4)]
+    n = [rt.fan_count(f) for f in fans]
+    per_ray = 7 * 8 + 2 * 4
+    srv = rt.Server(ctx, n_slots=4, mem_budget_bytes=max(n) * per_ray + 4096)
+    try:
+        ids = [srv.submit(grids[0], f, **opts("fp64")) for f in fans]
+        s = srv.stats()
+        assert s["running"] == 1 and s["queued"] == 3
+        order = []
+        out = {}
+        t0 = time.time()
+        while len(out) < len(ids):
+            for d in srv.poll():
+                order.append(d["id"])
+                out[d["id"]] = srv.fetch(d["id"], d["n_rays"])   # frees the arena block
+            assert time.time() - t0 < 60
+        assert order == ids
+    finally:
+        srv.close()
+    for rid, f in zip(ids, fans):
+        same(out[rid], rt.trace(ctx, grids[0], f, **opts("fp64")))
+
+
+def test_cancel_and_errors(rt, ctx, grids):
+    wl = synth.aniso_fan_workload(0)
+    fan = synth.sub_fan(wl.fan, elev_idx=list(range(0, 64, 4)), az_idx=list(range(0, 64, 4)))
+    n = rt.fan_count(fan)
+    srv = rt.Server(ctx, n_slots=1, mem_budget_bytes=1 << 20)
+    try:
+        a = srv.submit(grids[0], fan, **opts("fp64"))
+        b = srv.submit(grids[0], fan, **opts("fp64"))
+        c = srv.submit(grids[1], fan, **opts("mixed"))
+        srv.cancel(b)                                    # queued: dropped
+        srv.cancel(a)                                    # running: discarded on completion
+        done = drain(srv, 1)
+        assert list(done) == [c]
+        s = srv.stats()
+        assert s["queued"] == 0 and s["running"] == 0
+        out = srv.fetch(c, n)
+        same(out, rt.trace(ctx, grids[1], fan, **opts("mixed")))
+        assert srv.stats()["arena_used"] == 0
+        with pytest.raises(rt.RTError):
+            srv.fetch(c, n)                              # already fetched
+        with pytest.raises(rt.RTError):
+            srv.cancel(12345)
+        big = synth.sub_fan(wl.fan, elev_idx=list(range(64)), az_idx=list(range(64)))
+        with pytest.raises(rt.RTError) as e:
+            srv.submit(grids[0], big, **opts("fp64"))    # larger than the arena
+        assert e.value.code == rt.RT_E_NOMEM
+        empty = synth.Fan(30.0, 110.0, 0.0, np.zeros(0), np.zeros(1), np.array([10.0]), (1,))
+        z = srv.submit(grids[0], empty, **opts("fp64"))
+        assert [d["id"] for d in srv.poll()] == [z]
+        assert srv.fetch(z, 0)["status"].size == 0
+    finally:
+        srv.close()
