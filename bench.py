@@ -40,8 +40,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample-stride", type=int, default=16)
+    ap.add_argument("--cpu-sample-stride", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-qps", type=float, default=200.0)
     return ap.parse_args()
 
 
@@ -85,6 +87,30 @@ def main():
     fan_grid = rtgd.Grid(ctx, fan_wl.grid)
     fan64 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "fp64", max(3, a.steps), 1)
     fan32 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "mixed", max(3, a.steps), 1)
+    fan_grid.close()
+
+    serving = {}
+    if a.serve_requests > 0:
+        from paper_2506_18579_amd import serve
+        snaps = [rtgd.Grid(ctx, synth.ionosphere_grid(synth.GEOM_ANISO, s)) for s in range(4)]
+        reqs = synth.serving_requests(a.serve_requests, seed=1234, n_snapshots=4, max_rays=20000,
+                                      qps=a.serve_qps)
+        sopts = dict(step_km=1.0, max_group_km=4000.0, exit_h_km=600.0)
+        for prec in ("fp64", "mixed"):
+            srv = rtgd.Server(ctx, n_slots=4, mem_budget_bytes=256 << 20)
+            serve.replay(srv, snaps, reqs[:8], dict(sopts, precision=prec))      # warm-up
+            r = serve.replay(srv, snaps, reqs, dict(sopts, precision=prec))
+            srv.close()
+            lat = r["latency_s"] * 1e3
+            serving[prec] = {"ray_steps_per_s": float(r["ray_steps"].sum() / r["wall_s"]),
+                             "requests_per_s": len(reqs) / r["wall_s"],
+                             "latency_ms_p50": float(np.percentile(lat, 50)),
+                             "latency_ms_p99": float(np.percentile(lat, 99)),
+                             "latency_ms_max": float(lat.max()),
+                             "rays": int(r["rays"].sum()), "ray_steps": int(r["ray_steps"].sum()),
+                             "wall_s": r["wall_s"]}
+        for g in snaps:
+            g.close()
 
     steps_per_trace = fp64["ray_steps"] / a.steps
     ms_per_step = fp64["elapsed"] / a.steps * 1e3
@@ -112,21 +138,58 @@ def main():
         dt = time.perf_counter() - t
         cpu = {"value": o["total_steps"] / dt, "unit": "ray-steps/s", "cores": nthreads,
                "kind": "oracle",
-               "sample": f"every {a.cpu_sample_stride}th ray of the 112,400-ray ionogram sweep "
+               "sample": f"every {a.cpu_sample_stride}. ray of the 112,400-ray ionogram sweep "
                          f"({idx.size} rays, {o['total_steps']} ray-steps, {dt:.1f} s, "
                          f"plain FP64 C, OpenMP over rays)"}
         same = (res64["status"][idx] == o["status"])
         scale = lambda k, fl: np.abs(res64[k][idx][same] - o[k][same]) / np.maximum(np.abs(o[k][same]), fl)
-        rel = max(scale(k, 1.0).max() for k in ("group_km", "phase_km", "range_km", "az_dev_deg"))
-        accuracy["fp64_max_rel_vs_oracle"] = float(rel)
+        relv = np.max([scale(k, 1.0) for k in ("group_km", "phase_km", "range_km", "az_dev_deg")], axis=0)
+        accuracy["fp64_max_rel_vs_oracle"] = float(relv.max())
+        accuracy["fp64_median_rel_vs_oracle"] = float(np.median(relv))
+        accuracy["fp64_rays_over_1e-9_rel"] = int((relv > 1e-9).sum())
         accuracy["fp64_status_mismatch"] = int((~same).sum())
         same32 = (res32["status"][idx] == o["status"]) & (o["status"] != 3)
         for k in ("group_km", "range_km", "az_dev_deg"):
             d = res32[k][idx][same32] - o[k][same32]
-            accuracy[f"mixed_{k}_max"] = float(np.abs(d).max())
-            accuracy[f"mixed_{k}_rms"] = float(np.sqrt(np.mean(d * d)))
+            accuracy[f"mixed_{k}_max_all"] = float(np.abs(d).max())
+            accuracy[f"mixed_{k}_rms_all"] = float(np.sqrt(np.mean(d * d)))
         accuracy["mixed_status_mismatch"] = int((~same32 & (o["status"] != 3)).sum())
         accuracy["sample_rays"] = int(idx.size)
+        # FP32 evaluation perturbs every right-hand side at the 1e-7 level: a
+        # ray whose FP64 outputs already move by more than the tolerance when
+        # its elevation moves by 1e-6 deg or its frequency by 5e-8 (X by
+        # 1e-7) -- near the penetration boundary, near reflection -- is
+        # counted apart.  Probed on every 8th sampled ray.
+        sub = np.arange(0, idx.size, 8)
+        k_idx = idx[sub]
+        pe = np.concatenate([e[k_idx] - 1e-6, e[k_idx] + 1e-6, e[k_idx], e[k_idx]])
+        pf = np.concatenate([f[k_idx], f[k_idx], f[k_idx] * (1 - 5e-8), f[k_idx] * (1 + 5e-8)])
+        rep4 = lambda v: np.concatenate([v[k_idx]] * 4)
+        pr = O.trace(med, pe, rep4(az), pf, rep4(m), B0=wl.grid.B0_T,
+                     R=wl.grid.geom.earth_radius_km,
+                     tx=(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km),
+                     step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km,
+                     nthreads=nthreads)
+        ns = sub.size
+        ill = np.zeros(ns, dtype=bool)
+        for half in range(4):
+            sl = slice(half * ns, (half + 1) * ns)
+            ill |= pr["status"][sl] != o["status"][sub]
+            ill |= np.abs(pr["range_km"][sl] - o["range_km"][sub]) > 0.1
+            ill |= np.abs(pr["group_km"][sl] - o["group_km"][sub]) > 0.1
+            ill |= np.abs(pr["az_dev_deg"][sl] - o["az_dev_deg"][sub]) > 0.001
+        good = ~ill & (res32["status"][k_idx] == o["status"][sub]) & (o["status"][sub] != 3)
+        for k in ("group_km", "range_km", "az_dev_deg"):
+            d = res32[k][k_idx][good] - o[k][sub][good]
+            accuracy[f"mixed_{k}_max"] = float(np.abs(d).max())
+            accuracy[f"mixed_{k}_rms"] = float(np.sqrt(np.mean(d * d)))
+        within = good & (np.abs(res32["range_km"][k_idx] - o["range_km"][sub]) <= 0.1) & \
+            (np.abs(res32["group_km"][k_idx] - o["group_km"][sub]) <= 0.1) & \
+            (np.abs(res32["az_dev_deg"][k_idx] - o["az_dev_deg"][sub]) <= 0.001)
+        accuracy["mixed_conditioned_within_tolerance"] = int(within.sum())
+        accuracy["mixed_conditioned_rays"] = int(good.sum())
+        accuracy["mixed_ill_conditioned_rays"] = int(ill.sum())
+        accuracy["mixed_tolerance"] = "0.1 km ground range and group path, 0.001 deg azimuth"
 
     lat = np.array(fan64["walls"]) * 1e3
     lat32 = np.array(fan32["walls"]) * 1e3
@@ -163,10 +226,12 @@ def main():
             "fp64_latency_ms_p99": float(np.percentile(lat, 99)),
             "mixed_latency_ms_p50": float(np.percentile(lat32, 50)),
             "mixed_latency_ms_p99": float(np.percentile(lat32, 99))},
+        "serving": dict(serving, workload=f"Poisson {a.serve_qps:g} req/s, {a.serve_requests} "
+                        "fans of 1-20,000 rays (log-uniform), 4 resident 181x181x226 snapshots, "
+                        "4 slots, 256 MiB output arena") if serving else None,
     }
     print(json.dumps(line), flush=True)
     grid.close()
-    fan_grid.close()
     ctx.close()
 
 

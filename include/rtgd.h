@@ -206,10 +206,13 @@ rt_status rt_ionogram(rt_ctx *ctx, const rt_fan *fan, const rt_results *res, dou
  * A server owns n_slots HIP streams (each with its own workspace and pinned
  * staging) and a device-memory arena of mem_budget bytes for the outputs of
  * admitted requests.  rt_server_submit copies the fan and never blocks: the
- * request is launched at once if a slot is free and its outputs fit in the
- * arena, otherwise it waits in a FIFO queue.  rt_server_poll launches
- * queued requests as slots and memory free up and reports finished ones;
- * requests in different slots run concurrently on the device.  A finished
+ * request waits in a FIFO queue.  Whenever a slot is idle, the queue head
+ * and the requests behind it that share its grid geometry, transmitter and
+ * options and whose outputs fit in the arena are launched together as one
+ * batch on that slot (one persistent kernel over all their rays, each
+ * request through its own grid snapshot); launches in different slots run
+ * concurrently on the device.  rt_server_poll launches queued requests as
+ * slots and memory free up and reports finished ones.  A finished
  * request keeps its outputs in the arena until rt_server_fetch copies them
  * out and releases the memory.  Per-ray arithmetic does not depend on the
  * slot or on what else runs, so a request's results are bit-identical alone
@@ -220,9 +223,12 @@ rt_status rt_ionogram(rt_ctx *ctx, const rt_fan *fan, const rt_results *res, dou
 typedef struct rt_server rt_server;
 
 typedef struct {
-    int64_t mem_budget_bytes;  /* output arena; 0 = 256 MiB                  */
-    int32_t n_slots;           /* concurrent requests; 0 = 4                   */
-    int32_t reserved;          /* must be 0                                    */
+    int64_t mem_budget_bytes;  /* output arena; 0 = 256 MiB                    */
+    int32_t n_slots;           /* concurrent launches (streams); 0 = 4, <= 64    */
+    int32_t max_batch_requests;/* requests per launch; 0 = 256                   */
+    int32_t max_batch_rays;    /* rays per launch (a larger single request still
+                                  runs alone); 0 = 262144                        */
+    int32_t reserved;          /* must be 0                                      */
 } rt_server_opts;
 
 typedef struct {

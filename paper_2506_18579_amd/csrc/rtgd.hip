@@ -33,17 +33,31 @@ using namespace rtgd;
 namespace {
 
 // ---------------------------------------------------------------------------
-// Kernel parameters (passed by value)
+// Kernel parameters (one block in device memory per launch)
 // ---------------------------------------------------------------------------
+
+// One request of a launch: launch rays [start, start + n) are its fan, in
+// the order ((i_f * n_mode + i_m) * n_elev + i_e) * n_az + i_a.  A launch
+// holds one segment (rt_trace) or a batch of requests (the server) that
+// share the grid geometry, the transmitter and the step options.
+struct Segment {
+    const double *elev, *az, *freq;  // device copies of the fan axes
+    const void *v;                   // grid values (T) of the request's grid
+    double B0;                       // 0: isotropic
+    double *out[7];                  // group, phase, range, az_dev, apogee, land_lat, land_lon
+    int32_t *status, *nsteps;
+    unsigned long long *steps;       // RK4 steps of the request (accumulated)
+    int32_t n_elev, n_az, n_mode;
+    int32_t mode_first;              // +1 if the first mode is O, -1 if X
+    int32_t start, n;
+};
+
 template <typename T>
 struct TraceParams {
     GridDev<T> g;
-    double B0;                 // 0: isotropic
-    // fan: ray index = ((i_f * n_mode + i_m) * n_elev + i_e) * n_az + i_a
-    const double *elev, *az, *freq;
-    int32_t n_elev, n_az, n_freq, n_mode;
-    int32_t mode_first;        // +1 if the first mode is O, -1 if X
-    int32_t n_rays;
+    const Segment *seg;
+    int32_t n_seg;
+    int32_t n_rays;            // over all segments
     double tx_lon;             // rad
     double up[3], north[3], east[3];   // transmitter frame (Cartesian)
     double r0;                 // R + tx height
@@ -51,15 +65,10 @@ struct TraceParams {
     int32_t max_steps;         // hard cap (never reached before max_group)
     int32_t traj_stride;
     int64_t traj_per_ray;
-    // outputs (device)
-    double *group, *phase, *range, *azdev, *apogee, *land_lat, *land_lon;
-    int32_t *status, *nsteps;
-    double *traj;
+    double *traj;              // trajectories, indexed by launch ray (one segment only)
     int32_t *traj_count;
     // scheduling
-    const int32_t *order;      // ray visiting order (NULL: identity)
     int32_t *queue_head;
-    unsigned long long *total_steps;
     int32_t *truncated;
     // hand-off of the last live rays to the 4-lanes-per-ray tail kernel
     int32_t *live;             // rays neither finished nor handed off
@@ -133,6 +142,8 @@ struct Lane {
     RayConst rc;
     int32_t steps;
     int32_t ntraj;
+    int32_t seg;          // segment of the ray
+    int32_t local;        // ray index within the segment
 };
 
 template <typename T>
@@ -150,22 +161,33 @@ __device__ __forceinline__ void put_traj(const TraceParams<T> &P, int ray, Lane 
     }
 }
 
-// Per-ray constants from the ray index (fan decode).
+// Per-ray constants from the launch ray index: find the segment (binary
+// search over the segment starts), then decode its fan.
 template <typename T>
 __device__ __forceinline__ void ray_const(const TraceParams<T> &P, int ray, Lane &L, double &elev)
 {
-    int i = ray;
-    int ia = i % P.n_az; i /= P.n_az;
-    int ie = i % P.n_elev; i /= P.n_elev;
-    int im = i % P.n_mode; i /= P.n_mode;
+    int lo = 0, hi = P.n_seg - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (P.seg[mid].start <= ray) lo = mid;
+        else hi = mid - 1;
+    }
+    const Segment &S = P.seg[lo];
+    int i = ray - S.start;
+    L.seg = lo;
+    L.local = i;
+    int ia = i % S.n_az; i /= S.n_az;
+    int ie = i % S.n_elev; i /= S.n_elev;
+    int im = i % S.n_mode; i /= S.n_mode;
     int jf = i;
-    elev = P.elev[ie];
-    double f = P.freq[jf];
-    int sigma = (im == 0) ? P.mode_first : -1;
+    elev = S.elev[ie];
+    double f = S.freq[jf];
+    int sigma = (im == 0) ? S.mode_first : -1;
+    L.rc.v = S.v;
     L.rc.inv_f2 = 1.0 / (f * f);
-    L.rc.Y0 = kKB * P.B0 / (f * 1e6);
-    L.rc.sigma = (P.B0 == 0.0) ? 0 : sigma;
-    L.az0 = P.az[ia];
+    L.rc.Y0 = kKB * S.B0 / (f * 1e6);
+    L.rc.sigma = (S.B0 == 0.0) ? 0 : sigma;
+    L.az0 = S.az[ia];
 }
 
 // Ray initialisation (Sec. II-C): straight vacuum line from the transmitter
@@ -221,15 +243,14 @@ __device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray, Lan
 #pragma unroll
         for (int k = 0; k < 7; ++k) o[k] = __builtin_nan("");
     }
-    if (P.group) P.group[ray] = o[0];
-    if (P.phase) P.phase[ray] = o[1];
-    if (P.range) P.range[ray] = o[2];
-    if (P.azdev) P.azdev[ray] = o[3];
-    if (P.apogee) P.apogee[ray] = o[4];
-    if (P.land_lat) P.land_lat[ray] = o[5];
-    if (P.land_lon) P.land_lon[ray] = o[6];
-    if (P.status) P.status[ray] = status;
-    if (P.nsteps) P.nsteps[ray] = L.steps;
+    const Segment &S = P.seg[L.seg];
+    const int i = L.local;
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        if (S.out[k]) S.out[k][i] = o[k];
+    if (S.status) S.status[i] = status;
+    if (S.nsteps) S.nsteps[i] = L.steps;
+    atomicAdd(S.steps, (unsigned long long)L.steps);
     if (P.traj_count) P.traj_count[ray] = L.ntraj;
 }
 
@@ -324,14 +345,13 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
     Lane L;
     StencilCache<T, 1> sc;
     sc.clear();
-    unsigned long long my_steps = 0;
     for (int iter = 0;; ++iter) {
         bool need = (ray == -1);
         if (__ballot(need)) {
             int q = wave_append(P.queue_head, need, lane);
             if (need) {
                 if (q < P.n_rays) {
-                    ray = P.order ? P.order[q] : q;
+                    ray = q;
                     init_ray(P, ray, L, true);
                 } else {
                     ray = -2;
@@ -360,7 +380,6 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
                     H.steps = L.steps;
                     H.ntraj = L.ntraj;
                     H.pad = 0;
-                    my_steps += (unsigned long long)L.steps;
                     ray = -2;
                 }
                 unsigned long long hm = __ballot(hand);
@@ -373,16 +392,12 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
             st = advance<T, IP, 1>(P, ray, L, true, sc);
             if (st >= 0) {
                 finish_ray(P, ray, L, st);
-                my_steps += (unsigned long long)L.steps;
                 ray = -1;
             }
         }
         unsigned long long fin = __ballot(st >= 0);
         if (lane == 0 && fin && P.handoff_threshold > 0) atomicSub(P.live, __popcll(fin));
     }
-    // wave-reduce the step count, one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) my_steps += __shfl_down(my_steps, off);
-    if (lane == 0) atomicAdd(P.total_steps, my_steps);
 }
 
 // Tail kernel: four lanes (a quad) per handed-off ray.  The quad's lanes
@@ -415,22 +430,16 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
         L.steps = H.steps;
         L.ntraj = H.ntraj;
     }
-    unsigned long long my_steps = 0;
     for (;;) {
         if (__ballot(ray >= 0) == 0ull) break;
         if (ray >= 0) {
             int st = advance<T, IP, 4>(P, ray, L, lead, sc);
             if (st >= 0) {
-                if (lead) {
-                    finish_ray(P, ray, L, st);
-                    my_steps += (unsigned long long)(L.steps - P.handoff[slot].steps);
-                }
+                if (lead) finish_ray(P, ray, L, st);
                 ray = -1;
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) my_steps += __shfl_down(my_steps, off);
-    if (lane == 0) atomicAdd(P.total_steps, my_steps);
 }
 
 // Oblique-ionogram extraction: one thread per (frequency, mode) trace scans
@@ -745,10 +754,9 @@ rt_status rt_field_set(rt_grid *g, const rt_dipole *d)
 namespace {
 
 template <typename T>
-void fill_grid_dev(const rt_grid *grid, GridDev<T> &g, const T *v)
+void fill_grid_dev(const rt_grid *grid, GridDev<T> &g)
 {
     const rt_grid_geom &q = grid->geom;
-    g.v = v;
     g.n_lat = q.n_lat; g.n_lon = q.n_lon; g.n_h = q.n_h;
     g.lat0 = q.lat0_deg; g.lon0 = q.lon0_deg; g.h0 = q.h0_km;
     g.inv_dlat = 1.0 / q.dlat_deg; g.inv_dlon = 1.0 / q.dlon_deg; g.inv_dh = 1.0 / q.dh_km;
@@ -767,17 +775,25 @@ int resident_waves(rt_ctx *ctx, const void *kernel)
     return per_cu * ctx->n_cu;
 }
 
-// A validated trace request: the fan and options plus where its per-ray
-// outputs go on the device.
-struct TraceJob {
+// One validated request of a launch: its grid, fan (host arrays) and where
+// its per-ray outputs go on the device.
+struct JobSeg {
     const rt_grid *grid = nullptr;
     rt_fan fan{};
+    int n_rays = 0;
+    double *out[7] = {};       // group, phase, range, az_dev, apogee, land_lat, land_lon
+    int32_t *status = nullptr, *nsteps = nullptr;
+};
+
+// A launch: one or more requests that share the grid geometry, the
+// transmitter and the options.
+struct TraceJob {
+    std::vector<JobSeg> segs;
     rt_trace_opts opts{};
     int n_rays = 0;
     int tail = 0;              // hand-off threshold actually used
     int occ = 1;               // register budget variant
-    double *out[7] = {};       // group, phase, range, az_dev, apogee, land_lat, land_lon
-    int32_t *status = nullptr, *nsteps = nullptr, *tcount = nullptr;
+    int32_t *tcount = nullptr;
     double *traj = nullptr;
     int64_t per_ray = 0;
 };
@@ -785,15 +801,39 @@ struct TraceJob {
 static_assert(sizeof(TraceParams<float>) <= sizeof(TraceParams<double>),
               "the workspace reserves room for the FP64 parameter block");
 
-// Counters the kernels update, read back after a trace.
+// Counters the kernels update, read back after a launch (followed by one
+// step counter per segment).
 struct Counters {
     int32_t head, trunc, live, n_handoff;
-    unsigned long long total;
 };
 
-// Check a request; on success fill job (except the output pointers).
-rt_status validate_job(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
-                       const rt_trace_opts *opts, TraceJob &job)
+// Workspace layout of a launch, the same on the device and in host staging
+// (the hand-off buffer is device only): fan axes | segments | parameter
+// block | counters + per-segment steps | hand-off buffer.
+struct Layout {
+    size_t seg, par, cnt, steps, hand, host_bytes, dev_bytes;
+};
+
+size_t fan_values(const rt_fan &f) { return size_t(f.n_elev) + f.n_az + f.n_freq; }
+
+Layout job_layout(const TraceJob &j)
+{
+    size_t nf = 0;
+    for (const JobSeg &s : j.segs) nf += fan_values(s.fan);
+    Layout L;
+    L.seg = align_up(nf * 8, 256);
+    L.par = L.seg + align_up(j.segs.size() * sizeof(Segment), 256);
+    L.cnt = L.par + align_up(sizeof(TraceParams<double>), 256);
+    L.steps = L.cnt + align_up(sizeof(Counters), 64);
+    L.hand = L.steps + align_up(j.segs.size() * 8, 256);
+    L.host_bytes = L.hand;
+    L.dev_bytes = L.hand + size_t(j.tail) * sizeof(Handoff) + 256;
+    return L;
+}
+
+// Check one request; on success fill seg (except the output pointers).
+rt_status validate_request(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                           const rt_trace_opts *opts, JobSeg &seg)
 {
     if (!grid || !fan || !opts) return fail(ctx, RT_E_INVALID, "NULL argument");
     if (grid->ctx != ctx) return fail(ctx, RT_E_INVALID, "grid belongs to another context");
@@ -833,51 +873,53 @@ rt_status validate_job(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
         if (grid->B0 != 0.0 && f <= fH_max)
             return fail(ctx, RT_E_UNSUPPORTED, "frequency at or below the gyrofrequency (Y >= 1)");
     }
-    job.grid = grid;
-    job.fan = *fan;
-    job.opts = *opts;
-    job.n_rays = int(n64);
-    job.occ = opts->waves_per_simd == 0 ? 1 : opts->waves_per_simd;
-    int tail = opts->tail_threshold;
-    if (tail == 0) tail = ctx->n_cu * 64;     // library default
-    if (tail < 0) tail = 0;                   // hand-off off
-    job.tail = int(std::min<int64_t>(tail, n64));
-    job.per_ray = opts->traj_stride > 0 && n64 > 0 ? opts->traj_capacity / n64 : 0;
+    seg.grid = grid;
+    seg.fan = *fan;
+    seg.n_rays = int(n64);
     return RT_OK;
 }
 
-size_t fan_values(const rt_fan &f) { return size_t(f.n_elev) + f.n_az + f.n_freq; }
-
-// Device workspace: fan | parameter block | counters | hand-off buffer.
-size_t job_dev_bytes(const TraceJob &j)
+// Launch-wide settings from the options and the total ray count.
+void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
 {
-    return align_up(fan_values(j.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256) + 256 +
-           size_t(j.tail) * sizeof(Handoff) + 256;
+    job.opts = opts;
+    int64_t n64 = 0;
+    for (const JobSeg &s : job.segs) n64 += s.n_rays;
+    job.n_rays = int(n64);
+    job.occ = opts.waves_per_simd == 0 ? 1 : opts.waves_per_simd;
+    int tail = opts.tail_threshold;
+    if (tail == 0) tail = ctx->n_cu * 64;     // library default
+    if (tail < 0) tail = 0;                   // hand-off off
+    job.tail = int(std::min<int64_t>(tail, n64));
+    job.per_ray = opts.traj_stride > 0 && n64 > 0 ? opts.traj_capacity / n64 : 0;
 }
-// Host staging (pinned when the caller provides it): fan | params | counters.
-size_t job_host_bytes(const TraceJob &j)
+
+// Requests that can share one launch.
+bool compatible(const JobSeg &a, const rt_trace_opts &oa, const JobSeg &b, const rt_trace_opts &ob)
 {
-    return align_up(fan_values(j.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256) + 256;
+    const rt_grid_geom &x = a.grid->geom, &y = b.grid->geom;
+    return x.n_lat == y.n_lat && x.n_lon == y.n_lon && x.n_h == y.n_h && x.interp == y.interp &&
+           x.lat0_deg == y.lat0_deg && x.dlat_deg == y.dlat_deg && x.lon0_deg == y.lon0_deg &&
+           x.dlon_deg == y.dlon_deg && x.h0_km == y.h0_km && x.dh_km == y.dh_km &&
+           x.earth_radius_km == y.earth_radius_km && a.fan.tx_lat_deg == b.fan.tx_lat_deg &&
+           a.fan.tx_lon_deg == b.fan.tx_lon_deg && a.fan.tx_h_km == b.fan.tx_h_km &&
+           oa.step_km == ob.step_km && oa.max_group_km == ob.max_group_km &&
+           oa.exit_h_km == ob.exit_h_km && oa.precision == ob.precision &&
+           oa.tail_threshold == ob.tail_threshold && oa.waves_per_simd == ob.waves_per_simd &&
+           oa.traj_stride == 0 && ob.traj_stride == 0;
 }
 
 template <typename T>
-void fill_params(const TraceJob &job, TraceParams<T> &P, const double *d_fan, char *d_counters,
-                 Handoff *d_hand)
+void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char *dev)
 {
-    const rt_grid *grid = job.grid;
-    const rt_grid_geom &gq = grid->geom;
-    const rt_fan *fan = &job.fan;
+    const JobSeg &s0 = job.segs[0];
+    const rt_grid_geom &gq = s0.grid->geom;
+    const rt_fan *fan = &s0.fan;
     const rt_trace_opts *opts = &job.opts;
-    fill_grid_dev<T>(grid, P.g, sizeof(T) == 4 ? reinterpret_cast<const T *>(grid->d_f32)
-                                                : reinterpret_cast<const T *>(grid->d_f64));
+    fill_grid_dev<T>(s0.grid, P.g);
     const double la = fan->tx_lat_deg * kDeg2Rad, lo = fan->tx_lon_deg * kDeg2Rad;
-    P.B0 = grid->B0;
-    P.elev = d_fan;
-    P.az = d_fan + fan->n_elev;
-    P.freq = d_fan + fan->n_elev + fan->n_az;
-    P.n_elev = fan->n_elev; P.n_az = fan->n_az; P.n_freq = fan->n_freq;
-    P.n_mode = popcount_modes(fan->modes);
-    P.mode_first = (fan->modes & RT_MODE_O) ? 1 : -1;
+    P.seg = reinterpret_cast<const Segment *>(dev + lay.seg);
+    P.n_seg = int32_t(job.segs.size());
     P.n_rays = job.n_rays;
     P.tx_lon = lo;
     P.up[0] = std::cos(la) * std::cos(lo); P.up[1] = std::cos(la) * std::sin(lo); P.up[2] = std::sin(la);
@@ -892,77 +934,110 @@ void fill_params(const TraceJob &job, TraceParams<T> &P, const double *d_fan, ch
     P.max_steps = int32_t(std::ceil(opts->max_group_km / opts->step_km)) + 2;
     P.traj_stride = opts->traj_stride;
     P.traj_per_ray = job.per_ray;
-    P.group = job.out[0]; P.phase = job.out[1]; P.range = job.out[2]; P.azdev = job.out[3];
-    P.apogee = job.out[4]; P.land_lat = job.out[5]; P.land_lon = job.out[6];
-    P.status = job.status; P.nsteps = job.nsteps;
-    P.traj = job.traj; P.traj_count = job.tcount;
-    P.order = nullptr;
-    P.queue_head = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, head));
-    P.truncated = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, trunc));
-    P.live = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, live));
-    P.n_handoff = reinterpret_cast<int32_t *>(d_counters + offsetof(Counters, n_handoff));
-    P.total_steps = reinterpret_cast<unsigned long long *>(d_counters + offsetof(Counters, total));
-    P.handoff = d_hand;
+    P.traj = job.traj;
+    P.traj_count = job.tcount;
+    char *cnt = dev + lay.cnt;
+    P.queue_head = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, head));
+    P.truncated = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, trunc));
+    P.live = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, live));
+    P.n_handoff = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, n_handoff));
+    P.handoff = reinterpret_cast<Handoff *>(dev + lay.hand);
     P.handoff_threshold = job.tail;
 }
 
-// Enqueue one trace on `stream`: stage fan, parameter block and counters in
-// `host` (which must stay valid until the stream has consumed the copies),
-// copy them to `dev`, launch the one-lane persistent kernel and, with
-// hand-off on, the four-lane tail kernel; then copy the counters back into
-// host staging.  Events (optional) bracket the kernels.
+// Enqueue one launch on `stream`: stage fan axes, segment table, parameter
+// block and zeroed counters in `host` (which must stay valid until the
+// stream has consumed the copy), copy them to `dev` in one transfer, launch
+// the one-lane persistent kernel and, with hand-off on, the four-lane tail
+// kernel; then copy counters and per-segment step counts back into host
+// staging.  Events (optional) bracket the kernels.
 rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char *dev, char *host,
                       hipEvent_t ev0, hipEvent_t ev1)
 {
-    const size_t nf = fan_values(job.fan);
-    const size_t off_par = align_up(nf * 8, 256);
-    const size_t off_cnt = off_par + align_up(sizeof(TraceParams<double>), 256);
-    const size_t off_hand = off_cnt + 256;
+    const Layout lay = job_layout(job);
+    std::memset(host + lay.seg, 0, lay.host_bytes - lay.seg);
     double *h_fan = reinterpret_cast<double *>(host);
-    std::copy(job.fan.elev_deg, job.fan.elev_deg + job.fan.n_elev, h_fan);
-    std::copy(job.fan.az_deg, job.fan.az_deg + job.fan.n_az, h_fan + job.fan.n_elev);
-    std::copy(job.fan.freq_mhz, job.fan.freq_mhz + job.fan.n_freq, h_fan + job.fan.n_elev + job.fan.n_az);
+    Segment *h_seg = reinterpret_cast<Segment *>(host + lay.seg);
+    size_t off = 0;
+    int start = 0;
+    const bool mixed = job.opts.precision == RT_MIXED;
+    for (size_t k = 0; k < job.segs.size(); ++k) {
+        const JobSeg &js = job.segs[k];
+        const rt_fan &f = js.fan;
+        double *fe = h_fan + off;
+        std::copy(f.elev_deg, f.elev_deg + f.n_elev, fe);
+        std::copy(f.az_deg, f.az_deg + f.n_az, fe + f.n_elev);
+        std::copy(f.freq_mhz, f.freq_mhz + f.n_freq, fe + f.n_elev + f.n_az);
+        const double *de = reinterpret_cast<const double *>(dev) + off;
+        Segment &S = h_seg[k];
+        S.elev = de;
+        S.az = de + f.n_elev;
+        S.freq = de + f.n_elev + f.n_az;
+        S.v = mixed ? static_cast<const void *>(js.grid->d_f32) : static_cast<const void *>(js.grid->d_f64);
+        S.B0 = js.grid->B0;
+        for (int i = 0; i < 7; ++i) S.out[i] = js.out[i];
+        S.status = js.status;
+        S.nsteps = js.nsteps;
+        S.steps = reinterpret_cast<unsigned long long *>(dev + lay.steps) + k;
+        S.n_elev = f.n_elev;
+        S.n_az = f.n_az;
+        S.n_mode = popcount_modes(f.modes);
+        S.mode_first = (f.modes & RT_MODE_O) ? 1 : -1;
+        S.start = start;
+        S.n = js.n_rays;
+        start += js.n_rays;
+        off += fan_values(f);
+    }
     Counters hc{};
     hc.live = job.n_rays;
-    std::memcpy(host + off_cnt, &hc, sizeof(hc));
-    const double *d_fan = reinterpret_cast<const double *>(dev);
-    char *d_params = dev + off_par;
-    char *d_counters = dev + off_cnt;
-    Handoff *d_hand = reinterpret_cast<Handoff *>(dev + off_hand);
-    const bool cr = job.grid->geom.interp == RT_INTERP_CR;
+    std::memcpy(host + lay.cnt, &hc, sizeof(hc));
+    const bool cr = job.segs[0].grid->geom.interp == RT_INTERP_CR;
     const int occ = job.occ;
     const void *kt;
     const void *kl;
-    if (job.opts.precision == RT_MIXED) {
+    if (mixed) {
         TraceParams<float> P{};
-        fill_params<float>(job, P, d_fan, d_counters, d_hand);
-        std::memcpy(host + off_par, &P, sizeof(P));
+        fill_params<float>(job, lay, P, dev);
+        std::memcpy(host + lay.par, &P, sizeof(P));
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<float, 1> : (const void *)k_trace_w2<float, 0>)
                       : (cr ? (const void *)k_trace<float, 1> : (const void *)k_trace<float, 0>);
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<float, 1> : (const void *)k_tail_w2<float, 0>)
                       : (cr ? (const void *)k_tail<float, 1> : (const void *)k_tail<float, 0>);
     } else {
         TraceParams<double> P{};
-        fill_params<double>(job, P, d_fan, d_counters, d_hand);
-        std::memcpy(host + off_par, &P, sizeof(P));
+        fill_params<double>(job, lay, P, dev);
+        std::memcpy(host + lay.par, &P, sizeof(P));
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<double, 1> : (const void *)k_trace_w2<double, 0>)
                       : (cr ? (const void *)k_trace<double, 1> : (const void *)k_trace<double, 0>);
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<double, 1> : (const void *)k_tail_w2<double, 0>)
                       : (cr ? (const void *)k_tail<double, 1> : (const void *)k_tail<double, 0>);
     }
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(dev, host, off_hand, hipMemcpyHostToDevice, stream));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(dev, host, lay.host_bytes, hipMemcpyHostToDevice, stream));
     int max_waves = resident_waves<double>(ctx, kt);
     int waves = std::max(1, std::min((job.n_rays + 63) / 64, max_waves));
-    void *arg = d_params;
+    void *arg = dev + lay.par;
     void *args[] = {&arg};
     if (ev0) HIP_OR_FAIL(ctx, hipEventRecord(ev0, stream));
     HIP_OR_FAIL(ctx, hipLaunchKernel(kt, dim3(waves), dim3(64), args, 0, stream));
     if (job.tail > 0)
         HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 15) / 16), dim3(64), args, 0, stream));
     if (ev1) HIP_OR_FAIL(ctx, hipEventRecord(ev1, stream));
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(host + off_cnt, d_counters, sizeof(Counters),
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(host + lay.cnt, dev + lay.cnt, lay.hand - lay.cnt,
                                     hipMemcpyDeviceToHost, stream));
     return RT_OK;
+}
+
+// Read back what enqueue_job staged after the stream has finished.
+void job_counters(const TraceJob &job, const char *host, Counters &c, std::vector<int64_t> &steps)
+{
+    const Layout lay = job_layout(job);
+    std::memcpy(&c, host + lay.cnt, sizeof(c));
+    steps.resize(job.segs.size());
+    for (size_t k = 0; k < job.segs.size(); ++k) {
+        unsigned long long v;
+        std::memcpy(&v, host + lay.steps + 8 * k, 8);
+        steps[k] = int64_t(v);
+    }
 }
 
 rt_status ensure_pinned(rt_ctx *ctx, size_t bytes)
@@ -985,8 +1060,10 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     if (!ctx) return RT_E_INVALID;
     if (!res) return fail(ctx, RT_E_INVALID, "NULL argument");
     TraceJob job;
-    rt_status st = validate_job(ctx, grid, fan, opts, job);
+    job.segs.resize(1);
+    rt_status st = validate_request(ctx, grid, fan, opts, job.segs[0]);
     if (st != RT_OK) return st;
+    finish_job(ctx, job, *opts);
     res->total_steps = 0;
     res->kernel_ms = 0.0;
     if (job.n_rays == 0) return RT_OK;
@@ -994,16 +1071,18 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     if (opts->traj_stride > 0 && (!res->traj || opts->traj_capacity < n64))
         return fail(ctx, RT_E_INVALID, "trajectory needs traj and traj_capacity >= n_rays");
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-    if ((st = ensure_ws(ctx, job_dev_bytes(job))) != RT_OK) return st;
-    if ((st = ensure_pinned(ctx, job_host_bytes(job))) != RT_OK) return st;
+    const Layout lay = job_layout(job);
+    if ((st = ensure_ws(ctx, lay.dev_bytes)) != RT_OK) return st;
+    if ((st = ensure_pinned(ctx, lay.host_bytes)) != RT_OK) return st;
 
     const bool host_out = opts->results_mem == RT_MEM_HOST;
     const size_t N = size_t(job.n_rays);
     const int64_t per_ray = job.per_ray;
+    JobSeg &js = job.segs[0];
     double *dbl[7] = {res->group_km, res->phase_km, res->range_km, res->az_dev_deg,
                       res->apogee_km, res->land_lat_deg, res->land_lon_deg};
-    job.status = res->status;
-    job.nsteps = res->n_steps;
+    js.status = res->status;
+    js.nsteps = res->n_steps;
     job.tcount = res->traj_count;
     job.traj = per_ray > 0 ? res->traj : nullptr;
     if (host_out) {
@@ -1011,15 +1090,15 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
         if (per_ray > 0) bytes = align_up(bytes, 256) + size_t(per_ray) * N * 64;
         if ((st = ensure_stage(ctx, bytes)) != RT_OK) return st;
         char *sp = static_cast<char *>(ctx->stage);
-        for (int k = 0; k < 7; ++k) job.out[k] = dbl[k] ? reinterpret_cast<double *>(sp + k * N * 8) : nullptr;
+        for (int k = 0; k < 7; ++k) js.out[k] = dbl[k] ? reinterpret_cast<double *>(sp + k * N * 8) : nullptr;
         char *ip = sp + 7 * N * 8;
-        job.status = res->status ? reinterpret_cast<int32_t *>(ip) : nullptr;
-        job.nsteps = res->n_steps ? reinterpret_cast<int32_t *>(ip + N * 4) : nullptr;
+        js.status = res->status ? reinterpret_cast<int32_t *>(ip) : nullptr;
+        js.nsteps = res->n_steps ? reinterpret_cast<int32_t *>(ip + N * 4) : nullptr;
         job.tcount = res->traj_count ? reinterpret_cast<int32_t *>(ip + 2 * N * 4) : nullptr;
         job.traj = per_ray > 0 ? reinterpret_cast<double *>(sp + align_up(7 * N * 8 + 3 * N * 4 + 64, 256))
                                : nullptr;
     } else {
-        for (int k = 0; k < 7; ++k) job.out[k] = dbl[k];
+        for (int k = 0; k < 7; ++k) js.out[k] = dbl[k];
     }
     char *pinned = static_cast<char *>(ctx->pinned);
     if ((st = enqueue_job(ctx, ctx->stream, job, static_cast<char *>(ctx->ws), pinned, ctx->ev0,
@@ -1028,11 +1107,11 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     if (host_out) {
         for (int k = 0; k < 7; ++k)
             if (dbl[k])
-                HIP_OR_FAIL(ctx, hipMemcpyAsync(dbl[k], job.out[k], N * 8, hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(dbl[k], js.out[k], N * 8, hipMemcpyDeviceToHost, ctx->stream));
         if (res->status)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, job.status, N * 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, js.status, N * 4, hipMemcpyDeviceToHost, ctx->stream));
         if (res->n_steps)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, job.nsteps, N * 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, js.nsteps, N * 4, hipMemcpyDeviceToHost, ctx->stream));
         if (res->traj_count)
             HIP_OR_FAIL(ctx, hipMemcpyAsync(res->traj_count, job.tcount, N * 4, hipMemcpyDeviceToHost, ctx->stream));
         if (per_ray > 0)
@@ -1043,9 +1122,9 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     float ms = 0.f;
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     Counters hc;
-    const size_t off_cnt = align_up(fan_values(job.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256);
-    std::memcpy(&hc, pinned + off_cnt, sizeof(hc));
-    res->total_steps = int64_t(hc.total);
+    std::vector<int64_t> steps;
+    job_counters(job, pinned, hc, steps);
+    res->total_steps = steps[0];
     res->kernel_ms = ms;
     return hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
 }
@@ -1121,6 +1200,17 @@ namespace {
 // Per-ray outputs of one request inside the arena: 7 doubles + 2 int32.
 constexpr size_t kOutBytesPerRay = 7 * 8 + 2 * 4;
 
+struct Request {
+    int64_t id = 0;
+    JobSeg seg;                    // fan pointers refer to the vectors below
+    rt_trace_opts opts{};
+    std::vector<double> elev, az, freq;
+    size_t off = 0, bytes = 0;     // arena block
+    int state = 0;                 // 0 queued, 1 running, 2 done
+    bool cancelled = false;
+    rt_request_info info{};
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1128,20 +1218,8 @@ struct Slot {
     size_t dev_bytes = 0;
     char *host = nullptr;          // pinned
     size_t host_bytes = 0;
-    int64_t req = -1;              // running request, -1 idle
-};
-
-struct Request {
-    int64_t id = 0;
-    const rt_grid *grid = nullptr;
-    std::vector<double> elev, az, freq;
-    rt_fan fan{};
-    rt_trace_opts opts{};
+    std::vector<int64_t> reqs;     // requests of the running launch; empty when idle
     TraceJob job;
-    size_t off = 0, bytes = 0;     // arena block
-    int state = 0;                 // 0 queued, 1 running, 2 done
-    bool cancelled = false;
-    rt_request_info info{};
 };
 
 // First-fit allocator over the arena (offsets, host bookkeeping only).
@@ -1150,9 +1228,10 @@ struct Arena {
     size_t size = 0, used = 0;
     std::map<size_t, size_t> free_;   // offset -> length
     void init(char *b, size_t n) { base = b; size = n; free_.clear(); free_[0] = n; used = 0; }
+    static size_t round(size_t n) { return align_up(std::max<size_t>(n, 256), 256); }
     bool alloc(size_t n, size_t &off)
     {
-        n = align_up(std::max<size_t>(n, 256), 256);
+        n = round(n);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= n) {
                 off = it->first;
@@ -1167,7 +1246,7 @@ struct Arena {
     }
     void release(size_t off, size_t n)
     {
-        n = align_up(std::max<size_t>(n, 256), 256);
+        n = round(n);
         used -= n;
         auto it = free_.emplace(off, n).first;
         auto nx = std::next(it);
@@ -1193,8 +1272,10 @@ struct rt_server {
     Arena arena;
     std::deque<int64_t> queue;
     std::unordered_map<int64_t, Request> reqs;
-    std::vector<rt_request_info> done;
+    std::deque<rt_request_info> done;
     int64_t next_id = 1;
+    int max_batch_requests = 256;
+    int64_t max_batch_rays = 1 << 18;
 };
 
 namespace {
@@ -1212,39 +1293,67 @@ rt_status slot_reserve(rt_ctx *ctx, Slot &sl, size_t dev_bytes, size_t host_byte
         if (sl.host) (void)hipHostFree(sl.host);
         sl.host = nullptr;
         sl.host_bytes = 0;
-        HIP_OR_FAIL(ctx, hipHostMalloc(&sl.host, host_bytes, hipHostMallocDefault));
-        sl.host_bytes = host_bytes;
+        HIP_OR_FAIL(ctx, hipHostMalloc(&sl.host, std::max<size_t>(host_bytes, 1 << 16), hipHostMallocDefault));
+        sl.host_bytes = std::max<size_t>(host_bytes, 1 << 16);
     }
     return RT_OK;
 }
 
-// Launch queued requests in FIFO order while a slot is idle and the head
-// request's outputs fit in the arena.
+// Continuous batching: while a slot is idle, take from the head of the FIFO
+// queue every request that shares the head's geometry, transmitter and
+// options and whose outputs fit in the arena (up to the batch limits), and
+// launch them together on that slot's stream.  The head request waits, and
+// so does everything behind it, until the arena can hold its outputs.
 rt_status schedule(rt_server *srv)
 {
     while (!srv->queue.empty()) {
-        int slot = -1;
-        for (size_t i = 0; i < srv->slots.size(); ++i)
-            if (srv->slots[i].req < 0) { slot = int(i); break; }
-        if (slot < 0) return RT_OK;
-        Request &r = srv->reqs[srv->queue.front()];
-        if (!srv->arena.alloc(r.bytes, r.off)) return RT_OK;   // wait for memory
-        srv->queue.pop_front();
-        Slot &sl = srv->slots[slot];
-        rt_status st = slot_reserve(srv->ctx, sl, job_dev_bytes(r.job), job_host_bytes(r.job));
-        if (st != RT_OK) return st;
-        const size_t N = size_t(r.job.n_rays);
-        char *b = srv->arena.base + r.off;
-        for (int k = 0; k < 7; ++k) r.job.out[k] = reinterpret_cast<double *>(b + k * N * 8);
-        r.job.status = reinterpret_cast<int32_t *>(b + 7 * N * 8);
-        r.job.nsteps = reinterpret_cast<int32_t *>(b + 7 * N * 8 + N * 4);
-        r.job.fan.elev_deg = r.elev.data();
-        r.job.fan.az_deg = r.az.data();
-        r.job.fan.freq_mhz = r.freq.data();
-        st = enqueue_job(srv->ctx, sl.stream, r.job, sl.dev, sl.host, sl.ev0, sl.ev1);
-        if (st != RT_OK) return st;
-        sl.req = r.id;
-        r.state = 1;
+        Slot *slot = nullptr;
+        for (Slot &sl : srv->slots)
+            if (sl.reqs.empty()) { slot = &sl; break; }
+        if (!slot) return RT_OK;
+        std::vector<int64_t> ids;
+        int64_t rays = 0;
+        for (int64_t id : srv->queue) {
+            Request &r = srv->reqs[id];
+            if (!ids.empty()) {
+                const Request &h = srv->reqs[ids[0]];
+                if (!compatible(h.seg, h.opts, r.seg, r.opts)) break;
+                if (int(ids.size()) >= srv->max_batch_requests || rays + r.seg.n_rays > srv->max_batch_rays)
+                    break;
+            }
+            if (!srv->arena.alloc(r.bytes, r.off)) break;
+            ids.push_back(id);
+            rays += r.seg.n_rays;
+        }
+        if (ids.empty()) return RT_OK;                        // wait for memory
+        srv->queue.erase(srv->queue.begin(), srv->queue.begin() + ptrdiff_t(ids.size()));
+        TraceJob job;
+        for (int64_t id : ids) {
+            Request &r = srv->reqs[id];
+            const size_t N = size_t(r.seg.n_rays);
+            char *b = srv->arena.base + r.off;
+            for (int k = 0; k < 7; ++k) r.seg.out[k] = reinterpret_cast<double *>(b + k * N * 8);
+            r.seg.status = reinterpret_cast<int32_t *>(b + 7 * N * 8);
+            r.seg.nsteps = reinterpret_cast<int32_t *>(b + 7 * N * 8 + N * 4);
+            r.state = 1;
+            job.segs.push_back(r.seg);
+        }
+        finish_job(srv->ctx, job, srv->reqs[ids[0]].opts);
+        const Layout lay = job_layout(job);
+        rt_status st = slot_reserve(srv->ctx, *slot, lay.dev_bytes, lay.host_bytes);
+        if (st == RT_OK) st = enqueue_job(srv->ctx, slot->stream, job, slot->dev, slot->host, slot->ev0, slot->ev1);
+        if (st != RT_OK) {
+            // leave the requests queued at the head, in order, without memory
+            for (auto it = ids.rbegin(); it != ids.rend(); ++it) {
+                Request &r = srv->reqs[*it];
+                srv->arena.release(r.off, r.bytes);
+                r.state = 0;
+                srv->queue.push_front(*it);
+            }
+            return st;
+        }
+        slot->reqs = std::move(ids);
+        slot->job = std::move(job);
     }
     return RT_OK;
 }
@@ -1258,10 +1367,14 @@ extern "C" rt_status rt_server_create(rt_ctx *ctx, const rt_server_opts *opts, r
     int64_t budget = opts && opts->mem_budget_bytes > 0 ? opts->mem_budget_bytes : (int64_t(256) << 20);
     int n_slots = opts && opts->n_slots > 0 ? opts->n_slots : 4;
     if (n_slots > 64) return fail(ctx, RT_E_INVALID, "at most 64 slots");
+    if (opts && (opts->max_batch_requests < 0 || opts->max_batch_rays < 0))
+        return fail(ctx, RT_E_INVALID, "negative batch limit");
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     rt_server *srv = new (std::nothrow) rt_server();
     if (!srv) return fail(ctx, RT_E_NOMEM, "host allocation failed");
     srv->ctx = ctx;
+    if (opts && opts->max_batch_requests > 0) srv->max_batch_requests = opts->max_batch_requests;
+    if (opts && opts->max_batch_rays > 0) srv->max_batch_rays = opts->max_batch_rays;
     char *base = nullptr;
     hipError_t e = hipMalloc(&base, size_t(budget));
     if (e != hipSuccess) {
@@ -1271,7 +1384,7 @@ extern "C" rt_status rt_server_create(rt_ctx *ctx, const rt_server_opts *opts, r
     srv->arena.init(base, size_t(budget));
     srv->slots.resize(n_slots);
     for (auto &sl : srv->slots) {
-        // default priority on purpose
+        // non-blocking streams at the default priority
         if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
             (e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess) {
             rt_server_destroy(srv);
@@ -1305,31 +1418,34 @@ extern "C" rt_status rt_server_submit(rt_server *srv, const rt_grid *grid, const
     rt_ctx *ctx = srv->ctx;
     if (opts && opts->traj_stride != 0)
         return fail(ctx, RT_E_UNSUPPORTED, "the server does not record trajectories");
-    TraceJob job;
-    rt_status st = validate_job(ctx, grid, fan, opts, job);
-    if (st != RT_OK) return st;
     Request r;
+    rt_status st = validate_request(ctx, grid, fan, opts, r.seg);
+    if (st != RT_OK) return st;
+    r.bytes = size_t(r.seg.n_rays) * kOutBytesPerRay;
+    if (r.seg.n_rays > 0 && Arena::round(r.bytes) > srv->arena.size)
+        return fail(ctx, RT_E_NOMEM, "request larger than the arena");
     r.id = srv->next_id++;
-    r.grid = grid;
+    r.opts = *opts;
+    r.opts.results_mem = RT_MEM_DEVICE;
     r.elev.assign(fan->elev_deg, fan->elev_deg + fan->n_elev);
     r.az.assign(fan->az_deg, fan->az_deg + fan->n_az);
     r.freq.assign(fan->freq_mhz, fan->freq_mhz + fan->n_freq);
-    r.job = job;
-    r.job.opts.results_mem = RT_MEM_DEVICE;
-    r.bytes = size_t(job.n_rays) * kOutBytesPerRay;
-    if (r.bytes > srv->arena.size) return fail(ctx, RT_E_NOMEM, "request larger than the arena");
     r.info.id = r.id;
-    r.info.n_rays = job.n_rays;
+    r.info.n_rays = r.seg.n_rays;
     *id = r.id;
-    if (job.n_rays == 0) {      // empty fan: done at once
-        r.state = 2;
-        r.info.status = RT_OK;
-        srv->done.push_back(r.info);
-        srv->reqs.emplace(r.id, std::move(r));
+    const bool empty = r.seg.n_rays == 0;
+    auto it = srv->reqs.emplace(r.id, std::move(r)).first;
+    Request &q = it->second;
+    q.seg.fan.elev_deg = q.elev.data();
+    q.seg.fan.az_deg = q.az.data();
+    q.seg.fan.freq_mhz = q.freq.data();
+    if (empty) {                // empty fan: done at once
+        q.state = 2;
+        q.info.status = RT_OK;
+        srv->done.push_back(q.info);
         return RT_OK;
     }
-    srv->reqs.emplace(r.id, std::move(r));
-    srv->queue.push_back(*id);
+    srv->queue.push_back(q.id);
     return schedule(srv);
 }
 
@@ -1339,36 +1455,38 @@ extern "C" rt_status rt_server_poll(rt_server *srv, rt_request_info *done, int32
     rt_ctx *ctx = srv->ctx;
     *n_done = 0;
     for (auto &sl : srv->slots) {
-        if (sl.req < 0) continue;
+        if (sl.reqs.empty()) continue;
         hipError_t e = hipEventQuery(sl.ev1);
         if (e == hipErrorNotReady) continue;
         if (e != hipSuccess) return fail(ctx, RT_E_DEVICE, std::string("request: ") + hipGetErrorString(e));
-        // the counters copy follows ev1 on the stream
+        // the counter copy follows ev1 on the stream
         HIP_OR_FAIL(ctx, hipStreamSynchronize(sl.stream));
-        Request &r = srv->reqs[sl.req];
         Counters hc;
-        const size_t off_cnt = align_up(fan_values(r.job.fan) * 8, 256) + align_up(sizeof(TraceParams<double>), 256);
-        std::memcpy(&hc, sl.host + off_cnt, sizeof(hc));
+        std::vector<int64_t> steps;
+        job_counters(sl.job, sl.host, hc, steps);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, sl.ev0, sl.ev1);
-        r.info.total_steps = int64_t(hc.total);
-        r.info.kernel_ms = ms;
-        r.info.status = hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
-        r.state = 2;
-        sl.req = -1;
-        if (r.cancelled) {
-            srv->arena.release(r.off, r.bytes);
-            srv->reqs.erase(r.info.id);
-        } else {
-            srv->done.push_back(r.info);
+        for (size_t k = 0; k < sl.reqs.size(); ++k) {
+            Request &r = srv->reqs[sl.reqs[k]];
+            r.info.total_steps = steps[k];
+            r.info.kernel_ms = ms;
+            r.info.status = hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+            r.state = 2;
+            if (r.cancelled) {
+                srv->arena.release(r.off, r.bytes);
+                srv->reqs.erase(r.info.id);
+            } else {
+                srv->done.push_back(r.info);
+            }
         }
+        sl.reqs.clear();
     }
     rt_status st = schedule(srv);
     if (st != RT_OK) return st;
     int32_t k = 0;
     while (k < max && !srv->done.empty()) {
         done[k++] = srv->done.front();
-        srv->done.erase(srv->done.begin());
+        srv->done.pop_front();
     }
     *n_done = k;
     return RT_OK;
@@ -1384,17 +1502,17 @@ extern "C" rt_status rt_server_fetch(rt_server *srv, int64_t id, rt_results *res
     if (mem != RT_MEM_HOST && mem != RT_MEM_DEVICE)
         return fail(ctx, RT_E_INVALID, "mem must be RT_MEM_HOST or RT_MEM_DEVICE");
     Request &r = it->second;
-    const size_t N = size_t(r.job.n_rays);
+    const size_t N = size_t(r.seg.n_rays);
     if (N > 0) {
         hipMemcpyKind kind = mem == RT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
         double *dst[7] = {res->group_km, res->phase_km, res->range_km, res->az_dev_deg,
                           res->apogee_km, res->land_lat_deg, res->land_lon_deg};
         for (int k = 0; k < 7; ++k)
-            if (dst[k]) HIP_OR_FAIL(ctx, hipMemcpyAsync(dst[k], r.job.out[k], N * 8, kind, ctx->stream));
+            if (dst[k]) HIP_OR_FAIL(ctx, hipMemcpyAsync(dst[k], r.seg.out[k], N * 8, kind, ctx->stream));
         if (res->status)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, r.job.status, N * 4, kind, ctx->stream));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, r.seg.status, N * 4, kind, ctx->stream));
         if (res->n_steps)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, r.job.nsteps, N * 4, kind, ctx->stream));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, r.seg.nsteps, N * 4, kind, ctx->stream));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
         srv->arena.release(r.off, r.bytes);
     }
@@ -1423,7 +1541,7 @@ extern "C" rt_status rt_server_cancel(rt_server *srv, int64_t id)
     // finished but not fetched: release now
     for (auto d = srv->done.begin(); d != srv->done.end(); ++d)
         if (d->id == id) { srv->done.erase(d); break; }
-    if (r.job.n_rays > 0) srv->arena.release(r.off, r.bytes);
+    if (r.seg.n_rays > 0) srv->arena.release(r.off, r.bytes);
     srv->reqs.erase(it);
     return schedule(srv);
 }
@@ -1432,10 +1550,10 @@ extern "C" rt_status rt_server_stats(const rt_server *srv, int32_t *queued, int3
                                      int64_t *arena_used)
 {
     if (!srv) return RT_E_INVALID;
-    int run = 0;
-    for (auto &sl : srv->slots) run += sl.req >= 0;
+    size_t run = 0;
+    for (auto &sl : srv->slots) run += sl.reqs.size();
     if (queued) *queued = int32_t(srv->queue.size());
-    if (running) *running = run;
+    if (running) *running = int32_t(run);
     if (arena_used) *arena_used = int64_t(srv->arena.used);
     return RT_OK;
 }

@@ -33,11 +33,12 @@ constexpr double kKB = 2.799248983422872e10;
 
 enum RayStatus : int32_t { kGround = 0, kEscape = 1, kMaxPath = 2, kNumeric = 3 };
 
-// Grid geometry and values as the kernels see them.  Values are f_N^2 in
-// MHz^2 so that X = value / f_MHz^2.
+// Grid geometry as the kernels see it.  The values (f_N^2 in MHz^2, so
+// that X = value / f_MHz^2, laid out [n_lat][n_lon][n_h], height fastest)
+// are reached through each ray's RayConst::v: rays of one launch may run
+// through different grids of the same geometry.
 template <typename T>
 struct GridDev {
-    const T *v;                 // [n_lat][n_lon][n_h], height fastest
     int32_t n_lat, n_lon, n_h;
     double lat0, lon0, h0;      // first node (deg, deg, km)
     double inv_dlat, inv_dlon, inv_dh;
@@ -47,6 +48,7 @@ struct GridDev {
 
 // Per-ray constants.
 struct RayConst {
+    const void *v;   // grid values (T) of the ray's grid
     double inv_f2;   // 1 / f_MHz^2
     double Y0;       // f_H at the equatorial surface / f (0: no field)
     int32_t sigma;   // +1 O, -1 X, 0 isotropic
@@ -212,7 +214,8 @@ struct StencilCache {
     __device__ void clear() { il = -1; jl = -1; kh = -1; }
 };
 
-// f_N^2 (MHz^2) and its partials d/dr, d/dtheta, d/dphi at a position.
+// f_N^2 (MHz^2, returned in FP64) and its partials d/dr, d/dtheta, d/dphi
+// at a position.
 // Below the grid bottom the medium is vacuum; outside the box laterally or
 // above the top the value is continued as a constant.
 //
@@ -222,12 +225,13 @@ struct StencilCache {
 // the same order, ((row0 + row1) + (row2 + row3)), with the products
 // rounded separately, so the two give bit-identical results.
 template <typename T, int IP, int LANES>
-__device__ __forceinline__ void medium(const GridDev<T> &g, double r, double th, double ph,
-                                       StencilCache<T, LANES> &sc, T &F, T &Fr, T &Fth, T &Fph)
+__device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, double r, double th, double ph,
+                                       StencilCache<T, LANES> &sc, double &F, T &Fr, T &Fth, T &Fph)
 {
     double h = r - g.R;
     if (h < g.h0) {
-        F = Fr = Fth = Fph = T(0);
+        F = 0.0;
+        Fr = Fth = Fph = T(0);
         return;
     }
     double lat = fm(-th, kRad2Deg, 90.0);
@@ -246,7 +250,7 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, double r, double th,
 
     const size_t nh = size_t(g.n_h);
     const size_t row = size_t(g.n_lon) * nh;
-    gptr<T> base = (gptr<T>)(g.v) + (size_t(il - 1) * size_t(g.n_lon) + size_t(jl - 1)) * nh + size_t(kh - 1);
+    gptr<T> base = (gptr<T>)(vals) + (size_t(il - 1) * size_t(g.n_lon) + size_t(jl - 1)) * nh + size_t(kh - 1);
 
     // On a cell change, issue every load of this lane's share of the stencil
     // before any use, so that the memory round trips overlap (one wait
@@ -332,7 +336,9 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, double r, double th,
     }
     // index space -> physical: t_h = (r - R - h0)/dh,
     // t_lat = (90 - theta deg - lat0)/dlat, t_lon = (phi deg - lon0)/dlon
-    if constexpr (sizeof(T) == 4) F = v + uref;
+    // FP32: the base node value plus the contracted differences, summed in
+    // FP64 so that 1 - X keeps its relative accuracy where X -> 1
+    if constexpr (sizeof(T) == 4) F = double(v) + double(uref);
     else F = v;
     Fr = ch ? T(0) : gh * T(g.inv_dh);
     Fth = cl ? T(0) : glat * T(-kRad2Deg * g.inv_dlat);
@@ -340,13 +346,13 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, double r, double th,
 }
 
 // Appleton-Hartree partial derivatives of mu^2 with respect to X,
-// a = Y_T^2 and b = Y_L^2 (independent).  O mode from the factored
-// D = 2(1-X) E, E = 1 + 2b(1-X)/(S+a) (exact rearrangement, no cancellation
-// as X -> 1); X mode from D as printed.
+// a = Y_T^2 and b = Y_L^2 (independent), given X and u = 1 - X (formed by
+// the caller in FP64).  O mode from the factored D = 2(1-X) E,
+// E = 1 + 2b(1-X)/(S+a) (exact rearrangement, no cancellation as X -> 1);
+// X mode from D as printed.
 template <typename T>
-__device__ __forceinline__ void appleton_partials(T X, T a, T b, int sigma, T &mX, T &ma, T &mb)
+__device__ __forceinline__ void appleton_partials(T X, T u, T a, T b, int sigma, T &mX, T &ma, T &mb)
 {
-    T u = T(1) - X;
     T bu = b * u;
     T S = sqrt(fm(a, a, T(4) * bu * u));
     T iS = rcp(S);
@@ -355,7 +361,9 @@ __device__ __forceinline__ void appleton_partials(T X, T a, T b, int sigma, T &m
         T iT = rcp(Tt);
         T E = fm(T(2) * bu, iT, T(1));
         T iE = rcp(E);
-        T EX = T(2) * b * fm(T(4) * bu * u, iS, -Tt) * iT * iT;
+        // dE/dX = 2b (4bu^2/S - T)/T^2; with S^2 = a^2 + 4bu^2 the bracket is
+        // exactly -aT/S, so dE/dX = -2ab/(S T) (no cancellation when a << S)
+        T EX = T(-2) * a * b * iS * iT;
         T Ea = T(-2) * bu * iS * iT;
         T Eb = fm(T(-4) * bu * u * u * iS, iT * iT, T(2) * u * iT);
         T XiE2 = X * iE * iE;
@@ -384,10 +392,13 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
                                         double dy[7])
 {
     const double r = y[0], th = y[1], ph = y[2];
-    T F, Fr, Fth, Fph;
-    medium<T, IP, LANES>(g, r, th, ph, sc, F, Fr, Fth, Fph);
+    double F;
+    T Fr, Fth, Fph;
+    medium<T, IP, LANES>(g, static_cast<const T *>(rc.v), r, th, ph, sc, F, Fr, Fth, Fph);
     const T inv_f2 = T(rc.inv_f2);
-    const T X = F * inv_f2;
+    const double Xd = F * rc.inv_f2;
+    const T X = T(Xd);
+    const T u = T(1.0 - Xd);
     const T Xr = Fr * inv_f2, Xth = Fth * inv_f2, Xph = Fph * inv_f2;
 
     const T rr = T(r);
@@ -412,9 +423,12 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
         const T Yn = fm(Y0, nr, Y1 * nt);
         const T in2 = rcp(n2);
         const T b = Yn * Yn * in2;
-        const T a = Y2 - b;
+        // Y_T^2 = |Y x n|^2 / n^2 directly, rather than Y^2 - Y_L^2, which
+        // cancels for near-longitudinal propagation
+        const T cz = fm(Y0, nt, -(Y1 * nr));
+        const T a = fm(cz, cz, np * np * Y2) * in2;
         T mX, ma, mba;
-        appleton_partials<T>(X, a, b, rc.sigma, mX, ma, mba);
+        appleton_partials<T>(X, u, a, b, rc.sigma, mX, ma, mba);
         const T mY2 = ma;            // d mu^2 / d Y^2 at fixed b
         const T mb = mba - ma;       // d mu^2 / d b at fixed Y^2
         G = fm(X, mX, fm(Y2, mY2, fm(b, mb, -n2)));

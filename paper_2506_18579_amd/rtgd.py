@@ -73,6 +73,7 @@ class Results(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("n_slots", ctypes.c_int32),
+                ("max_batch_requests", ctypes.c_int32), ("max_batch_rays", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -378,15 +379,17 @@ def ionogram(ctx: Context, fan, res, range_km: float, max_points: int = 8):
 
 class Server:
     """Request server (rt_server_*): continuous batching of ray-fan
-    requests over `n_slots` streams with a device output arena of
-    `mem_budget_bytes`.  submit() never blocks; poll() launches queued work
+    requests (queued requests are launched together, as slots free up) over
+    `n_slots` streams with a device output arena of `mem_budget_bytes`.  submit() never blocks; poll() launches queued work
     and returns finished requests; fetch() copies a finished request's
     per-ray outputs out and frees its arena block."""
 
-    def __init__(self, ctx: Context, n_slots: int = 4, mem_budget_bytes: int = 256 << 20):
+    def __init__(self, ctx: Context, n_slots: int = 4, mem_budget_bytes: int = 256 << 20,
+                 max_batch_requests: int = 0, max_batch_rays: int = 0):
         self.ctx = ctx
         self.h = ctypes.c_void_p()
-        so = ServerOpts(int(mem_budget_bytes), int(n_slots), 0)
+        so = ServerOpts(int(mem_budget_bytes), int(n_slots), int(max_batch_requests),
+                        int(max_batch_rays), 0)
         ctx.check(lib().rt_server_create(ctx.h, ctypes.byref(so), ctypes.byref(self.h)),
                   "rt_server_create")
         self._n = {}
