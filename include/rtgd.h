@@ -262,6 +262,56 @@ rt_status rt_server_cancel(rt_server *srv, int64_t id);
 rt_status rt_server_stats(const rt_server *srv, int32_t *queued, int32_t *running,
                           int64_t *arena_used);
 
+/* ------------------------------------------------------------------------
+ * Replayable traces (HIP graph).  rt_plan_create validates a trace exactly
+ * like rt_trace, stages its fan and parameter block once, and captures the
+ * launch sequence (workspace upload, one-lane kernel, four-lane tail
+ * kernel, counter read-back) into a HIP graph on a private stream.  The
+ * plan owns its workspace and pinned staging; it borrows the grid and the
+ * caller's result buffers, which must be device memory (opts->results_mem =
+ * RT_MEM_DEVICE) and stay valid, like the grid, until rt_plan_destroy.
+ * The fan is copied at create.  Trajectories are not supported.
+ * rt_plan_launch enqueues one replay on the context's stream and returns;
+ * rt_plan_wait synchronizes that stream and reports the replay's ray-steps
+ * and device time.  Every replay recomputes all outputs from the launch
+ * state (the counters are re-uploaded by the graph, no memset nodes).
+ * ---------------------------------------------------------------------- */
+typedef struct rt_plan rt_plan;
+
+rt_status rt_plan_create(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                         const rt_trace_opts *opts, const rt_results *res, rt_plan **out);
+rt_status rt_plan_launch(rt_plan *plan);
+rt_status rt_plan_wait(rt_plan *plan, int64_t *total_steps, double *kernel_ms);
+void rt_plan_destroy(rt_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Autotuner.  The launch settings that change speed but not results are the
+ * hand-off threshold of the four-lane tail kernel (tail_threshold) and the
+ * register budget of the one-lane kernel (waves_per_simd).  rt_autotune
+ * traces the given fan once per candidate setting (tail_threshold in
+ * {off, 16, 64, 256 rays per CU} x waves_per_simd in {1, 2}), keeps the
+ * fastest by device time and writes base with those two fields replaced to
+ * *tuned.  Choices are cached in the process under a key made of the
+ * device's CU count, the grid shape and interpolation, precision, field on
+ * or off and the ray count rounded to a power of two; a cached key is
+ * answered without tracing.  Results of the trial traces are discarded
+ * (every candidate gives bit-identical results).  rt_tune_cache_save and
+ * rt_tune_cache_load write and read the cache as text, one key per line.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double best_ms;            /* device time of the chosen setting (0 if cached) */
+    double default_ms;         /* device time with the library defaults (0 if cached) */
+    int32_t n_candidates;      /* settings traced                                */
+    int32_t from_cache;        /* 1: answered from the cache                     */
+} rt_tune_info;
+
+rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan, const rt_trace_opts *base,
+                      rt_trace_opts *tuned, rt_tune_info *info);
+/* RT_E_INVALID if the file cannot be written / read or a line is malformed. */
+rt_status rt_tune_cache_save(const char *path);
+rt_status rt_tune_cache_load(const char *path);
+void rt_tune_cache_clear(void);
+
 /* Host-only helpers (no device needed). */
 rt_status rt_fan_count(const rt_fan *fan, int64_t *n_rays);
 rt_status rt_check_geom(const rt_grid_geom *geom);

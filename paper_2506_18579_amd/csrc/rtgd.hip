@@ -17,6 +17,10 @@
 #include <cstddef>
 #include <deque>
 #include <map>
+#include <mutex>
+#include <tuple>
+#include <fstream>
+#include <sstream>
 #include <unordered_map>
 #include <cmath>
 #include <cstdio>
@@ -949,10 +953,12 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
 // block and zeroed counters in `host` (which must stay valid until the
 // stream has consumed the copy), copy them to `dev` in one transfer, launch
 // the one-lane persistent kernel and, with hand-off on, the four-lane tail
-// kernel; then copy counters and per-segment step counts back into host
-// staging.  Events (optional) bracket the kernels.
+// kernel; then copy counters and per-segment step counts back to
+// `readback` (host, readback_bytes(job) bytes; NULL: into host staging,
+// which a replayed upload must not see).  Events (optional) bracket the
+// kernels.
 rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char *dev, char *host,
-                      hipEvent_t ev0, hipEvent_t ev1)
+                      hipEvent_t ev0, hipEvent_t ev1, char *readback = nullptr)
 {
     const Layout lay = job_layout(job);
     std::memset(host + lay.seg, 0, lay.host_bytes - lay.seg);
@@ -1022,20 +1028,29 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     if (job.tail > 0)
         HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 15) / 16), dim3(64), args, 0, stream));
     if (ev1) HIP_OR_FAIL(ctx, hipEventRecord(ev1, stream));
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(host + lay.cnt, dev + lay.cnt, lay.hand - lay.cnt,
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(readback ? readback : host + lay.cnt, dev + lay.cnt, lay.hand - lay.cnt,
                                     hipMemcpyDeviceToHost, stream));
     return RT_OK;
 }
 
-// Read back what enqueue_job staged after the stream has finished.
-void job_counters(const TraceJob &job, const char *host, Counters &c, std::vector<int64_t> &steps)
+size_t readback_bytes(const TraceJob &job)
 {
     const Layout lay = job_layout(job);
-    std::memcpy(&c, host + lay.cnt, sizeof(c));
+    return lay.hand - lay.cnt;
+}
+
+// Counters and per-segment step counts after the stream has finished;
+// `readback` as given to enqueue_job (NULL: host staging).
+void job_counters(const TraceJob &job, const char *host, Counters &c, std::vector<int64_t> &steps,
+                  const char *readback = nullptr)
+{
+    const Layout lay = job_layout(job);
+    const char *rb = readback ? readback : host + lay.cnt;
+    std::memcpy(&c, rb, sizeof(c));
     steps.resize(job.segs.size());
     for (size_t k = 0; k < job.segs.size(); ++k) {
         unsigned long long v;
-        std::memcpy(&v, host + lay.steps + 8 * k, 8);
+        std::memcpy(&v, rb + (lay.steps - lay.cnt) + 8 * k, 8);
         steps[k] = int64_t(v);
     }
 }
@@ -1556,4 +1571,279 @@ extern "C" rt_status rt_server_stats(const rt_server *srv, int32_t *queued, int3
     if (running) *running = int32_t(run);
     if (arena_used) *arena_used = int64_t(srv->arena.used);
     return RT_OK;
+}
+
+// ===========================================================================
+// Replayable traces (HIP graph)
+// ===========================================================================
+struct rt_plan {
+    rt_ctx *ctx = nullptr;
+    TraceJob job;
+    std::vector<double> elev, az, freq;
+    char *dev = nullptr;
+    char *host = nullptr;          // pinned staging, read by every replay
+    char *readback = nullptr;      // pinned, counters written by every replay
+    hipStream_t cap = nullptr;     // private capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool launched = false;
+};
+
+extern "C" void rt_plan_destroy(rt_plan *p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    if (p->launched) (void)hipStreamSynchronize(p->ctx->stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    if (p->dev) (void)hipFree(p->dev);
+    if (p->host) (void)hipHostFree(p->host);
+    if (p->readback) (void)hipHostFree(p->readback);
+    delete p;
+}
+
+extern "C" rt_status rt_plan_create(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                                    const rt_trace_opts *opts, const rt_results *res, rt_plan **out)
+{
+    if (!ctx) return RT_E_INVALID;
+    if (!res || !out) return fail(ctx, RT_E_INVALID, "NULL argument");
+    *out = nullptr;
+    rt_plan *p = new (std::nothrow) rt_plan();
+    if (!p) return fail(ctx, RT_E_NOMEM, "host allocation failed");
+    p->ctx = ctx;
+    p->job.segs.resize(1);
+    JobSeg &js = p->job.segs[0];
+    rt_status st = validate_request(ctx, grid, fan, opts, js);
+    if (st == RT_OK && opts->traj_stride != 0) st = fail(ctx, RT_E_UNSUPPORTED, "plans do not record trajectories");
+    if (st == RT_OK && opts->results_mem != RT_MEM_DEVICE)
+        st = fail(ctx, RT_E_INVALID, "plans write device results (results_mem = RT_MEM_DEVICE)");
+    if (st == RT_OK && js.n_rays == 0) st = fail(ctx, RT_E_INVALID, "empty fan");
+    if (st != RT_OK) {
+        delete p;
+        return st;
+    }
+    p->elev.assign(fan->elev_deg, fan->elev_deg + fan->n_elev);
+    p->az.assign(fan->az_deg, fan->az_deg + fan->n_az);
+    p->freq.assign(fan->freq_mhz, fan->freq_mhz + fan->n_freq);
+    js.fan.elev_deg = p->elev.data();
+    js.fan.az_deg = p->az.data();
+    js.fan.freq_mhz = p->freq.data();
+    double *dbl[7] = {res->group_km, res->phase_km, res->range_km, res->az_dev_deg,
+                      res->apogee_km, res->land_lat_deg, res->land_lon_deg};
+    for (int k = 0; k < 7; ++k) js.out[k] = dbl[k];
+    js.status = res->status;
+    js.nsteps = res->n_steps;
+    finish_job(ctx, p->job, *opts);
+    const Layout lay = job_layout(p->job);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc(&p->dev, lay.dev_bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&p->host, lay.host_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&p->readback, readback_bytes(p->job), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev1);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        rt_plan_destroy(p);
+        return fail(ctx, e == hipErrorOutOfMemory ? RT_E_NOMEM : RT_E_DEVICE,
+                    std::string("plan setup: ") + hipGetErrorString(e));
+    }
+    // staging is filled here and read again by every replay's upload node
+    st = enqueue_job(ctx, p->cap, p->job, p->dev, p->host, nullptr, nullptr, p->readback);
+    e = hipStreamEndCapture(p->cap, &p->graph);
+    if (st == RT_OK && e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (st != RT_OK || e != hipSuccess) {
+        rt_plan_destroy(p);
+        return st != RT_OK ? st : fail(ctx, RT_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *out = p;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_launch(rt_plan *p)
+{
+    if (!p) return RT_E_INVALID;
+    rt_ctx *ctx = p->ctx;
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    HIP_OR_FAIL(ctx, hipEventRecord(p->ev0, ctx->stream));
+    HIP_OR_FAIL(ctx, hipGraphLaunch(p->exec, ctx->stream));
+    HIP_OR_FAIL(ctx, hipEventRecord(p->ev1, ctx->stream));
+    p->launched = true;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_plan_wait(rt_plan *p, int64_t *total_steps, double *kernel_ms)
+{
+    if (!p) return RT_E_INVALID;
+    rt_ctx *ctx = p->ctx;
+    if (!p->launched) return fail(ctx, RT_E_INVALID, "plan not launched");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    p->launched = false;
+    Counters hc;
+    std::vector<int64_t> steps;
+    job_counters(p->job, p->host, hc, steps, p->readback);
+    float ms = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    if (total_steps) *total_steps = steps[0];
+    if (kernel_ms) *kernel_ms = ms;
+    return RT_OK;
+}
+
+// ===========================================================================
+// Autotuner
+// ===========================================================================
+namespace {
+
+struct TuneKey {
+    int32_t n_cu, n_lat, n_lon, n_h, interp, precision, field, log2_rays;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(n_cu, n_lat, n_lon, n_h, interp, precision, field, log2_rays) <
+               std::tie(o.n_cu, o.n_lat, o.n_lon, o.n_h, o.interp, o.precision, o.field, o.log2_rays);
+    }
+};
+struct TuneVal {
+    int32_t tail_threshold, waves_per_simd;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
+int ceil_log2(int64_t n)
+{
+    int k = 0;
+    while ((int64_t(1) << k) < n) ++k;
+    return k;
+}
+
+}  // namespace
+
+extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                                 const rt_trace_opts *base, rt_trace_opts *tuned, rt_tune_info *info)
+{
+    if (!ctx) return RT_E_INVALID;
+    if (!tuned) return fail(ctx, RT_E_INVALID, "NULL argument");
+    JobSeg probe;
+    rt_status st = validate_request(ctx, grid, fan, base, probe);
+    if (st != RT_OK) return st;
+    if (base->traj_stride != 0) return fail(ctx, RT_E_UNSUPPORTED, "tune without trajectories");
+    rt_tune_info inf{};
+    *tuned = *base;
+    const TuneKey key{ctx->n_cu, grid->geom.n_lat, grid->geom.n_lon, grid->geom.n_h, grid->geom.interp,
+                      base->precision, grid->B0 != 0.0 ? 1 : 0, ceil_log2(std::max(probe.n_rays, 1))};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            tuned->tail_threshold = it->second.tail_threshold;
+            tuned->waves_per_simd = it->second.waves_per_simd;
+            inf.from_cache = 1;
+            if (info) *info = inf;
+            return RT_OK;
+        }
+    }
+    if (probe.n_rays == 0) {
+        if (info) *info = inf;
+        return RT_OK;
+    }
+    // scratch outputs on the device (discarded)
+    const size_t N = size_t(probe.n_rays);
+    char *buf = nullptr;
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    HIP_OR_FAIL(ctx, hipMalloc(&buf, N * (7 * 8 + 2 * 4) + 256));
+    rt_results r{};
+    r.group_km = reinterpret_cast<double *>(buf);
+    r.phase_km = r.group_km + N; r.range_km = r.group_km + 2 * N; r.az_dev_deg = r.group_km + 3 * N;
+    r.apogee_km = r.group_km + 4 * N; r.land_lat_deg = r.group_km + 5 * N; r.land_lon_deg = r.group_km + 6 * N;
+    r.status = reinterpret_cast<int32_t *>(buf + 7 * N * 8);
+    r.n_steps = r.status + N;
+    const int tails[4] = {-1, ctx->n_cu * 16, ctx->n_cu * 64, ctx->n_cu * 256};
+    const int occs[2] = {1, 2};
+    auto time_opts = [&](rt_trace_opts o, double &ms) -> rt_status {
+        o.results_mem = RT_MEM_DEVICE;
+        ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {     // first run warms caches and code
+            rt_status s2 = rt_trace(ctx, grid, fan, &o, &r);
+            if (s2 != RT_OK) return s2;
+            ms = rep ? std::min(ms, r.kernel_ms) : ms;
+        }
+        return RT_OK;
+    };
+    double best = 1e300;
+    TuneVal bv{0, 0};
+    rt_trace_opts o = *base;
+    o.tail_threshold = 0;
+    o.waves_per_simd = 0;
+    st = time_opts(o, inf.default_ms);
+    for (int oc : occs) {
+        for (int tl : tails) {
+            if (st != RT_OK) break;
+            o.tail_threshold = tl;
+            o.waves_per_simd = oc;
+            double ms = 0;
+            st = time_opts(o, ms);
+            ++inf.n_candidates;
+            if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc}; }
+        }
+    }
+    (void)hipFree(buf);
+    if (st != RT_OK) return st;
+    inf.best_ms = best;
+    tuned->tail_threshold = bv.tail_threshold;
+    tuned->waves_per_simd = bv.waves_per_simd;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = bv;
+    }
+    if (info) *info = inf;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_tune_cache_save(const char *path)
+{
+    if (!path) return RT_E_INVALID;
+    std::ofstream f(path);
+    if (!f) return RT_E_INVALID;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    f << "# n_cu n_lat n_lon n_h interp precision field log2_rays -> tail_threshold waves_per_simd\n";
+    for (const auto &kv : g_tune_cache) {
+        const TuneKey &k = kv.first;
+        f << k.n_cu << ' ' << k.n_lat << ' ' << k.n_lon << ' ' << k.n_h << ' ' << k.interp << ' '
+          << k.precision << ' ' << k.field << ' ' << k.log2_rays << ' ' << kv.second.tail_threshold << ' '
+          << kv.second.waves_per_simd << '\n';
+    }
+    return f.good() ? RT_OK : RT_E_INVALID;
+}
+
+extern "C" rt_status rt_tune_cache_load(const char *path)
+{
+    if (!path) return RT_E_INVALID;
+    std::ifstream f(path);
+    if (!f) return RT_E_INVALID;
+    std::map<TuneKey, TuneVal> loaded;
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ss(line);
+        TuneKey k{};
+        TuneVal v{};
+        if (!(ss >> k.n_cu >> k.n_lat >> k.n_lon >> k.n_h >> k.interp >> k.precision >> k.field >>
+              k.log2_rays >> v.tail_threshold >> v.waves_per_simd))
+            return RT_E_INVALID;
+        if (v.waves_per_simd < 0 || v.waves_per_simd > 2 || v.tail_threshold > (1 << 24)) return RT_E_INVALID;
+        loaded[k] = v;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : loaded) g_tune_cache[kv.first] = kv.second;
+    return RT_OK;
+}
+
+extern "C" void rt_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
 }

@@ -83,6 +83,11 @@ class RequestInfo(ctypes.Structure):
                 ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("n_candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+
+
 OUT_DOUBLE = ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km",
               "land_lat_deg", "land_lon_deg")
 OUT_INT = ("status", "n_steps")
@@ -152,6 +157,24 @@ def lib():
     L.rt_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int64)]
     L.rt_server_stats.restype = ctypes.c_int32
+    L.rt_plan_create.argtypes = [vp, vp, ctypes.POINTER(Fan), ctypes.POINTER(TraceOpts),
+                                 ctypes.POINTER(Results), ctypes.POINTER(vp)]
+    L.rt_plan_create.restype = ctypes.c_int32
+    L.rt_plan_launch.argtypes = [vp]
+    L.rt_plan_launch.restype = ctypes.c_int32
+    L.rt_plan_wait.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    L.rt_plan_wait.restype = ctypes.c_int32
+    L.rt_plan_destroy.argtypes = [vp]
+    L.rt_plan_destroy.restype = None
+    L.rt_autotune.argtypes = [vp, vp, ctypes.POINTER(Fan), ctypes.POINTER(TraceOpts),
+                              ctypes.POINTER(TraceOpts), ctypes.POINTER(TuneInfo)]
+    L.rt_autotune.restype = ctypes.c_int32
+    L.rt_tune_cache_save.argtypes = [ctypes.c_char_p]
+    L.rt_tune_cache_save.restype = ctypes.c_int32
+    L.rt_tune_cache_load.argtypes = [ctypes.c_char_p]
+    L.rt_tune_cache_load.restype = ctypes.c_int32
+    L.rt_tune_cache_clear.argtypes = []
+    L.rt_tune_cache_clear.restype = None
     _lib = L
     return L
 
@@ -445,6 +468,79 @@ class Server:
     def close(self):
         if self.h:
             lib().rt_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
+             precision="fp64") -> dict:
+    """rt_autotune: the fastest (tail_threshold, waves_per_simd) for this
+    fan, from the process cache or by timing every candidate."""
+    fa = FanArgs(fan)
+    base = make_opts(step_km, max_group_km, exit_h_km, precision)
+    tuned = TraceOpts()
+    info = TuneInfo()
+    ctx.check(lib().rt_autotune(ctx.h, grid.h, ctypes.byref(fa.s), ctypes.byref(base),
+                                ctypes.byref(tuned), ctypes.byref(info)), "rt_autotune")
+    return dict(tail_threshold=int(tuned.tail_threshold), waves_per_simd=int(tuned.waves_per_simd),
+                best_ms=float(info.best_ms), default_ms=float(info.default_ms),
+                n_candidates=int(info.n_candidates), from_cache=bool(info.from_cache))
+
+
+def tune_cache_save(path: str):
+    if lib().rt_tune_cache_save(os.fsencode(path)) != RT_OK:
+        raise RTError(RT_E_INVALID, f"cannot write {path}")
+
+
+def tune_cache_load(path: str):
+    if lib().rt_tune_cache_load(os.fsencode(path)) != RT_OK:
+        raise RTError(RT_E_INVALID, f"cannot read {path} or a line is malformed")
+
+
+def tune_cache_clear():
+    lib().rt_tune_cache_clear()
+
+
+class Plan:
+    """A trace captured once into a HIP graph (rt_plan_*) and replayed.
+    Results go to device tensors (self.out), rewritten by every replay."""
+
+    def __init__(self, ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0,
+                 exit_h_km=0.0, precision="fp64", tail_threshold=0, waves_per_simd=0):
+        import torch
+        self.ctx, self.grid = ctx, grid
+        n = fan_count(fan)
+        dev = torch.device("cuda", ctx.device)
+        self.out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in OUT_DOUBLE}
+        self.out.update({k: torch.empty(n, dtype=torch.int32, device=dev) for k in OUT_INT})
+        r = Results()
+        for k in OUT_DOUBLE:
+            setattr(r, k, ctypes.cast(ctypes.c_void_p(self.out[k].data_ptr()), _DP))
+        for k in OUT_INT:
+            setattr(r, k, ctypes.cast(ctypes.c_void_p(self.out[k].data_ptr()), _IP))
+        o = make_opts(step_km, max_group_km, exit_h_km, precision, tail_threshold, waves_per_simd)
+        o.results_mem = RT_MEM_DEVICE
+        fa = FanArgs(fan)
+        self.h = ctypes.c_void_p()
+        ctx.check(lib().rt_plan_create(ctx.h, grid.h, ctypes.byref(fa.s), ctypes.byref(o),
+                                       ctypes.byref(r), ctypes.byref(self.h)), "rt_plan_create")
+
+    def launch(self):
+        self.ctx.check(lib().rt_plan_launch(self.h), "rt_plan_launch")
+
+    def wait(self):
+        steps, ms = ctypes.c_int64(0), ctypes.c_double(0.0)
+        self.ctx.check(lib().rt_plan_wait(self.h, ctypes.byref(steps), ctypes.byref(ms)), "rt_plan_wait")
+        return int(steps.value), float(ms.value)
+
+    def close(self):
+        if self.h:
+            lib().rt_plan_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):

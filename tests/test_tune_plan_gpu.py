@@ -1,0 +1,110 @@
+"""Autotuner and HIP-graph plans on the GPU.
+
+The autotuner only changes launch settings that do not change results, so
+a trace with the tuned settings equals the default trace bit for bit; a
+second call is answered from the cache.  A plan replays the captured
+launch sequence: every replay, with other eager work and synchronization
+between replays, must equal the eager rt_trace result bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_18579_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "land_lat_deg",
+        "land_lon_deg", "status", "n_steps")
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2506_18579_amd import rtgd
+    rtgd.lib()
+    return rtgd
+
+
+@pytest.fixture(scope="module")
+def ctx(rt):
+    c = rt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def wl():
+    return synth.aniso_fan_workload(0)
+
+
+@pytest.fixture(scope="module")
+def grid(rt, ctx, wl):
+    g = rt.Grid(ctx, wl.grid)
+    yield g
+    g.close()
+
+
+def host(d):
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in d.items()}
+
+
+def test_autotune_choice_is_cached_and_result_neutral(rt, ctx, grid, wl, tmp_path):
+    fan = synth.sub_fan(wl.fan, elev_idx=list(range(0, 64, 2)), az_idx=list(range(0, 64, 4)))
+    kw = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km)
+    rt.tune_cache_clear()
+    t = rt.autotune(ctx, grid, fan, precision="mixed", **kw)
+    assert not t["from_cache"] and t["n_candidates"] == 8
+    assert t["waves_per_simd"] in (1, 2)
+    assert t["tail_threshold"] in (-1, 256 * 16, 256 * 64, 256 * 256) or t["tail_threshold"] % 16 == 0
+    assert 0 < t["best_ms"] <= 1.5 * t["default_ms"]
+    t2 = rt.autotune(ctx, grid, fan, precision="mixed", **kw)
+    assert t2["from_cache"] and (t2["tail_threshold"], t2["waves_per_simd"]) == \
+        (t["tail_threshold"], t["waves_per_simd"])
+    p = tmp_path / "tune.txt"
+    rt.tune_cache_save(str(p))
+    rt.tune_cache_clear()
+    rt.tune_cache_load(str(p))
+    assert rt.autotune(ctx, grid, fan, precision="mixed", **kw)["from_cache"]
+    a = rt.trace(ctx, grid, fan, precision="mixed", **kw)
+    b = rt.trace(ctx, grid, fan, precision="mixed", tail_threshold=t["tail_threshold"],
+                 waves_per_simd=t["waves_per_simd"], **kw)
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plan_replays_equal_eager(rt, ctx, grid, wl, precision):
+    fan = synth.sub_fan(wl.fan, elev_idx=list(range(0, 64, 3)), az_idx=list(range(0, 64, 5)))
+    kw = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km,
+              precision=precision)
+    eager = rt.trace(ctx, grid, fan, **kw)
+    plan = rt.Plan(ctx, grid, fan, **kw)
+    other = synth.sub_fan(wl.fan, elev_idx=[1, 30], az_idx=[2, 60])
+    try:
+        for rep in range(3):
+            for v in plan.out.values():
+                v.fill_(-7)            # a replay must rewrite every output
+            plan.launch()
+            steps, ms = plan.wait()
+            got = host(plan.out)
+            assert steps == eager["total_steps"] and ms > 0
+            for k in KEYS:
+                assert np.array_equal(got[k], eager[k], equal_nan=True), (rep, k)
+            rt.trace(ctx, grid, other, **kw)          # eager work between replays
+    finally:
+        plan.close()
+
+
+def test_plan_rejects_host_results_and_empty_fans(rt, ctx, grid, wl):
+    import ctypes
+    fan = synth.sub_fan(wl.fan, elev_idx=[0], az_idx=[0])
+    fa = rt.FanArgs(fan)
+    o = rt.make_opts(precision="fp64")
+    o.results_mem = rt.RT_MEM_HOST
+    r = rt.Results()
+    h = ctypes.c_void_p()
+    st = rt.lib().rt_plan_create(ctx.h, grid.h, ctypes.byref(fa.s), ctypes.byref(o), ctypes.byref(r),
+                                 ctypes.byref(h))
+    assert st == rt.RT_E_INVALID
+    empty = synth.Fan(30.0, 110.0, 0.0, np.zeros(0), np.zeros(1), np.array([10.0]), (1,))
+    with pytest.raises(rt.RTError):
+        rt.Plan(ctx, grid, empty)
