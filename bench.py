@@ -34,6 +34,26 @@ FLOPS_PER_STEP_ISO = 4 * 617 + 136
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (256 CU x 2.4 GHz x 128)
 PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 
+# HBM bytes of one FP64 ionogram launch (k_trace + k_tail) from rocprofv3:
+# FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB device copy
+# in the same runs).  Valid only for the kernel sources with these hashes;
+# otherwise the traffic is reported as null.
+TRAFFIC_BYTES = (32288 + 23643) * 1024
+TRAFFIC_SOURCES = {
+    "rtgd.hip": "7795b99e7612e01719bbf30a915ea0646a2de9796de24be4a0cc885dda6afe22",
+    "rtgd_device.h": "f5917413459a0d487d9f757027151259853bf3cc605d55d5b77f80fa142033a0",
+}
+
+
+def measured_traffic():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2506_18579_amd", "csrc")
+    for name, digest in TRAFFIC_SOURCES.items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return TRAFFIC_BYTES
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -43,22 +63,24 @@ def parse():
     ap.add_argument("--cpu-sample-stride", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-qps", type=float, default=200.0,
+                    help="rate the request stream is drawn at (rescaled to each offered load)")
     return ap.parse_args()
 
 
-def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup):
+def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup, tune=None):
     out = None
+    kw = dict(tail_threshold=tune["tail_threshold"], waves_per_simd=tune["waves_per_simd"]) if tune else {}
     for _ in range(warmup):
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
-                         exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out)
+                         exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out, **kw)
     torch.cuda.synchronize()
     walls, kms, total = [], [], 0
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
-                         exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out)
+                         exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out, **kw)
         walls.append(time.perf_counter() - ts)
         kms.append(out["kernel_ms"])
         total += out["total_steps"]
@@ -70,9 +92,9 @@ def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: rays are independent and this build "
-              "measures the single-GPU shard (see DESIGN.md for how it would shard).",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: rays are independent, so one GPU's share of a "
+              "sharded fan is the same workload at its real shape; multi-GPU runs are not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2506_18579_amd import rtgd, synth
@@ -81,8 +103,11 @@ def main():
     wl = synth.ionogram_workload(0)
     grid = rtgd.Grid(ctx, wl.grid)
 
-    fp64 = time_trace(rtgd, torch, ctx, grid, wl, "fp64", a.steps, a.warmup)
-    mixed = time_trace(rtgd, torch, ctx, grid, wl, "mixed", max(1, a.steps), 1)
+    wkw = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km)
+    tune64 = rtgd.autotune(ctx, grid, wl.fan, precision="fp64", **wkw)
+    tune32 = rtgd.autotune(ctx, grid, wl.fan, precision="mixed", **wkw)
+    fp64 = time_trace(rtgd, torch, ctx, grid, wl, "fp64", a.steps, a.warmup, tune64)
+    mixed = time_trace(rtgd, torch, ctx, grid, wl, "mixed", max(1, a.steps), 1, tune32)
     fan_wl = synth.aniso_fan_workload(0)
     fan_grid = rtgd.Grid(ctx, fan_wl.grid)
     fan64 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "fp64", max(3, a.steps), 1)
@@ -96,19 +121,33 @@ def main():
         reqs = synth.serving_requests(a.serve_requests, seed=1234, n_snapshots=4, max_rays=20000,
                                       qps=a.serve_qps)
         sopts = dict(step_km=1.0, max_group_km=4000.0, exit_h_km=600.0)
+        burst = [dict(q, t_arrive=0.0) for q in reqs]
+
+        def stats(r):
+            lat = r["latency_s"] * 1e3
+            return {"ray_steps_per_s": float(r["ray_steps"].sum() / r["wall_s"]),
+                    "requests_per_s": len(reqs) / r["wall_s"],
+                    "latency_ms_p50": float(np.percentile(lat, 50)),
+                    "latency_ms_p99": float(np.percentile(lat, 99)),
+                    "latency_ms_max": float(lat.max()), "wall_s": r["wall_s"]}
         for prec in ("fp64", "mixed"):
             srv = rtgd.Server(ctx, n_slots=4, mem_budget_bytes=256 << 20)
-            serve.replay(srv, snaps, reqs[:8], dict(sopts, precision=prec))      # warm-up
-            r = serve.replay(srv, snaps, reqs, dict(sopts, precision=prec))
+            o = dict(sopts, precision=prec)
+            serve.replay(srv, snaps, reqs[:8], o)                       # warm-up
+            # saturation: every request queued at t = 0
+            rs = serve.replay(srv, snaps, burst, o)
+            sat = stats(rs)
+            res = dict(rays=int(rs["rays"].sum()), ray_steps=int(rs["ray_steps"].sum()),
+                       saturation=sat)
+            # Poisson arrivals (the same stream, time-scaled) at 25, 50 and 90 % of
+            # the measured saturation request rate
+            for frac in (0.25, 0.5, 0.9):
+                qps = frac * sat["requests_per_s"]
+                scaled = [dict(q, t_arrive=q["t_arrive"] * a.serve_qps / qps) for q in reqs]
+                res[f"load_{int(frac * 100)}pct"] = dict(stats(serve.replay(srv, snaps, scaled, o)),
+                                                         offered_requests_per_s=qps)
             srv.close()
-            lat = r["latency_s"] * 1e3
-            serving[prec] = {"ray_steps_per_s": float(r["ray_steps"].sum() / r["wall_s"]),
-                             "requests_per_s": len(reqs) / r["wall_s"],
-                             "latency_ms_p50": float(np.percentile(lat, 50)),
-                             "latency_ms_p99": float(np.percentile(lat, 99)),
-                             "latency_ms_max": float(lat.max()),
-                             "rays": int(r["rays"].sum()), "ray_steps": int(r["ray_steps"].sum()),
-                             "wall_s": r["wall_s"]}
+            serving[prec] = res
         for g in snaps:
             g.close()
 
@@ -212,8 +251,10 @@ def main():
                    "max_group_km": wl.max_group_km},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS,
-                     "traffic": None, "kernel": "k_trace<double>",
+                     "traffic": measured_traffic(),
+                     "kernel": "trace launch: k_trace<double,0> + k_tail<double,0>",
                      "kernel_ms_avg": kms, "flops_per_ray_step": FLOPS_PER_STEP_ANISO},
+        "tuning": {"fp64": tune64, "mixed": tune32},
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "mixed": {"value": mixed["ray_steps"] / mixed["elapsed"],
@@ -226,9 +267,10 @@ def main():
             "fp64_latency_ms_p99": float(np.percentile(lat, 99)),
             "mixed_latency_ms_p50": float(np.percentile(lat32, 50)),
             "mixed_latency_ms_p99": float(np.percentile(lat32, 99))},
-        "serving": dict(serving, workload=f"Poisson {a.serve_qps:g} req/s, {a.serve_requests} "
-                        "fans of 1-20,000 rays (log-uniform), 4 resident 181x181x226 snapshots, "
-                        "4 slots, 256 MiB output arena") if serving else None,
+        "serving": dict(serving, workload=f"{a.serve_requests} fans of 1-20,000 rays "
+                        "(log-uniform), 4 resident 181x181x226 snapshots, 4 slots, 256 MiB output "
+                        "arena; all requests at once (saturation), then Poisson arrivals at 25, "
+                        "50 and 90 % of the saturation request rate") if serving else None,
     }
     print(json.dumps(line), flush=True)
     grid.close()
