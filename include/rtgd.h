@@ -115,8 +115,8 @@ typedef struct {
     int64_t traj_capacity;  /* records available in rt_results.traj        */
     int32_t results_mem;    /* RT_MEM_HOST or RT_MEM_DEVICE                */
     int32_t tail_threshold; /* scheduling knob, results unchanged: once the
-                               queue is empty and fewer rays than this are
-                               live, each is finished by four lanes instead
+                               queue is empty and at most this many rays are
+                               live, each is finished by 16 lanes instead
                                of one; 0 = library default, < 0 = never   */
     int32_t waves_per_simd; /* scheduling knob, results unchanged: register
                                budget of the kernels, 1 = whole register
@@ -265,7 +265,7 @@ rt_status rt_server_stats(const rt_server *srv, int32_t *queued, int32_t *runnin
 /* ------------------------------------------------------------------------
  * Replayable traces (HIP graph).  rt_plan_create validates a trace exactly
  * like rt_trace, stages its fan and parameter block once, and captures the
- * launch sequence (workspace upload, one-lane kernel, four-lane tail
+ * launch sequence (workspace upload, one-lane kernel, 16-lane tail
  * kernel, counter read-back) into a HIP graph on a private stream.  The
  * plan owns its workspace and pinned staging; it borrows the grid and the
  * caller's result buffers, which must be device memory (opts->results_mem =
@@ -286,10 +286,10 @@ void rt_plan_destroy(rt_plan *plan);
 
 /* ------------------------------------------------------------------------
  * Autotuner.  The launch settings that change speed but not results are the
- * hand-off threshold of the four-lane tail kernel (tail_threshold) and the
+ * hand-off threshold of the 16-lane tail kernel (tail_threshold) and the
  * register budget of the one-lane kernel (waves_per_simd).  rt_autotune
  * traces the given fan once per candidate setting (tail_threshold in
- * {off, 16, 64, 256 rays per CU} x waves_per_simd in {1, 2}), keeps the
+ * {off, 8, 16, 32 rays per CU} x waves_per_simd in {1, 2}), keeps the
  * fastest by device time and writes base with those two fields replaced to
  * *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on

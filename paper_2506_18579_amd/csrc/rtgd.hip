@@ -78,10 +78,11 @@ struct TraceParams {
     int32_t *live;             // rays neither finished nor handed off
     int32_t *n_handoff;        // records written
     struct Handoff *handoff;   // capacity handoff_threshold
-    int32_t handoff_threshold; // hand off once fewer rays than this are live (0: never)
+    int32_t handoff_threshold; // hand off once at most this many rays are live (0: never);
+                               // also the hand-off buffer capacity
 };
 
-// State of a ray moved from the one-lane to the four-lane kernel.
+// State of a ray moved from the one-lane to the sixteen-lane kernel.
 struct Handoff {
     double y[7];
     double gp, apogee;
@@ -259,8 +260,8 @@ __device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray, Lan
 }
 
 // One RK4 step plus the termination tests.  Returns the ray status, or -1
-// if the ray goes on.  `write` is false on the lanes of a quad that only
-// shadow the quad's leader (no memory writes).
+// if the ray goes on.  `write` is false on the lanes of a row that only
+// shadow the row's leader (no memory writes).
 template <typename T, int IP, int LANES>
 __device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L, bool write,
                                        StencilCache<T, LANES> &sc)
@@ -336,9 +337,9 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred, int lane
 // Persistent one-lane-per-ray kernel.  Each 64-lane wave loops { refill
 // idle lanes from the queue; one RK4 step on every live lane } until the
 // queue is drained and every lane is idle.  When the queue is drained and
-// fewer than handoff_threshold rays are live, each remaining ray's state is
+// at most handoff_threshold rays are live, each remaining ray's state is
 // written to the hand-off buffer and the lane retires (the tail kernel
-// finishes it with four lanes per ray).  Every ray terminates (the group
+// finishes it with sixteen lanes per ray).  Every ray terminates (the group
 // path grows by one step per iteration up to max_group), so every wave exits.
 template <typename T, int IP>
 __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp)
@@ -371,7 +372,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
             }
             live = __shfl(live, 0);
             head = __shfl(head, 0);
-            if (head >= P.n_rays && live < P.handoff_threshold) {
+            if (head >= P.n_rays && live <= P.handoff_threshold) {
                 bool hand = ray >= 0;
                 int slot = wave_append(P.n_handoff, hand, lane);
                 if (hand) {
@@ -404,24 +405,26 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
     }
 }
 
-// Tail kernel: four lanes (a quad) per handed-off ray.  The quad's lanes
-// hold identical state and run identical arithmetic; only the stencil
-// contraction is split (one latitude row per lane, see medium<T, 4>), so
-// the results equal the one-lane kernel's bit for bit.  Lane 0 of the quad
-// writes.  Launched with enough quads for the hand-off capacity; quads past
-// the number of records exit at once.
+// Tail kernel: sixteen lanes (a DPP row) per handed-off ray, four rays per
+// wave.  The row's lanes hold identical state and run identical arithmetic;
+// only the stencil contraction is split (one column per lane, see
+// medium<T, IP, 16>), so the results equal the one-lane kernel's bit for
+// bit.  Lane 0 of the row writes.  Launched with enough rows for the
+// hand-off capacity; rows past the number of records exit at once.
 template <typename T, int IP>
 __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
 {
     const TraceParams<T> &P = *Pp;
     const int lane = int(__lane_id());
-    const int slot = int(blockIdx.x) * 16 + (lane >> 2);
-    const bool lead = (lane & 3) == 0;
+    const int slot = int(blockIdx.x) * 4 + (lane >> 4);
+    const bool lead = (lane & 15) == 0;
     const int n = *P.n_handoff;
     int ray = -1;
     Lane L;
-    StencilCache<T, 4> sc;
+    StencilCache<T, 16> sc;
     sc.clear();
+    sc.pa = piece<T, IP>((lane >> 2) & 3);
+    sc.pb = piece<T, IP>(lane & 3);
     if (slot < n) {
         const Handoff &H = P.handoff[slot];
         ray = H.ray;
@@ -437,7 +440,7 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
     for (;;) {
         if (__ballot(ray >= 0) == 0ull) break;
         if (ray >= 0) {
-            int st = advance<T, IP, 4>(P, ray, L, lead, sc);
+            int st = advance<T, IP, 16>(P, ray, L, lead, sc);
             if (st >= 0) {
                 if (lead) finish_ray(P, ray, L, st);
                 ray = -1;
@@ -892,7 +895,7 @@ void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
     job.n_rays = int(n64);
     job.occ = opts.waves_per_simd == 0 ? 1 : opts.waves_per_simd;
     int tail = opts.tail_threshold;
-    if (tail == 0) tail = ctx->n_cu * 64;     // library default
+    if (tail == 0) tail = ctx->n_cu * 16;     // library default: 4 SIMDs x 4 rays per wave per CU
     if (tail < 0) tail = 0;                   // hand-off off
     job.tail = int(std::min<int64_t>(tail, n64));
     job.per_ray = opts.traj_stride > 0 && n64 > 0 ? opts.traj_capacity / n64 : 0;
@@ -952,7 +955,7 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
 // Enqueue one launch on `stream`: stage fan axes, segment table, parameter
 // block and zeroed counters in `host` (which must stay valid until the
 // stream has consumed the copy), copy them to `dev` in one transfer, launch
-// the one-lane persistent kernel and, with hand-off on, the four-lane tail
+// the one-lane persistent kernel and, with hand-off on, the sixteen-lane tail
 // kernel; then copy counters and per-segment step counts back to
 // `readback` (host, readback_bytes(job) bytes; NULL: into host staging,
 // which a replayed upload must not see).  Events (optional) bracket the
@@ -1026,7 +1029,7 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     if (ev0) HIP_OR_FAIL(ctx, hipEventRecord(ev0, stream));
     HIP_OR_FAIL(ctx, hipLaunchKernel(kt, dim3(waves), dim3(64), args, 0, stream));
     if (job.tail > 0)
-        HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 15) / 16), dim3(64), args, 0, stream));
+        HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 3) / 4), dim3(64), args, 0, stream));
     if (ev1) HIP_OR_FAIL(ctx, hipEventRecord(ev1, stream));
     HIP_OR_FAIL(ctx, hipMemcpyAsync(readback ? readback : host + lay.cnt, dev + lay.cnt, lay.hand - lay.cnt,
                                     hipMemcpyDeviceToHost, stream));
@@ -1761,7 +1764,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     r.apogee_km = r.group_km + 4 * N; r.land_lat_deg = r.group_km + 5 * N; r.land_lon_deg = r.group_km + 6 * N;
     r.status = reinterpret_cast<int32_t *>(buf + 7 * N * 8);
     r.n_steps = r.status + N;
-    const int tails[4] = {-1, ctx->n_cu * 16, ctx->n_cu * 64, ctx->n_cu * 256};
+    const int tails[4] = {-1, ctx->n_cu * 8, ctx->n_cu * 16, ctx->n_cu * 32};
     const int occs[2] = {1, 2};
     auto time_opts = [&](rt_trace_opts o, double &ms) -> rt_status {
         o.results_mem = RT_MEM_DEVICE;

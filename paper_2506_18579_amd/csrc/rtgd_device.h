@@ -19,7 +19,7 @@
 namespace rtgd {
 
 // Device code is compiled with FP contraction off: every fused multiply-add
-// is written out, so that every kernel variant (one or four lanes per ray)
+// is written out, so that every kernel variant (one or sixteen lanes per ray)
 // performs the same rounded operations in the same order.
 __device__ __forceinline__ double fm(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fm(float a, float b, float c) { return fmaf(a, b, c); }
@@ -55,56 +55,83 @@ struct RayConst {
 };
 
 // ---------------------------------------------------------------------------
-// 1-D weights for node offsets a = -1, 0, 1, 2 of the cell containing s.
-// GD p=3: the four Appendix A quintic pieces, node j+a taking piece -a in
-// its shifted variable s (Horner form).
+// 1-D weights for node offsets a = -1, 0, 1, 2 (index 0..3) of the cell
+// containing s.  GD p = 3: node j+a takes the Appendix A piece psi_{-a} in
+// its shifted variable, a quintic in s; Catmull-Rom (eq. cr_basis): a cubic.
+// Every weight is evaluated in the same full Horner form from its monomial
+// coefficients (w = ((c5 s + c4) s + ...) s + c0, w' from 5 c5, 4 c4, ...),
+// so a lane that evaluates a single node's piece from coefficients held in
+// registers rounds exactly as a lane that evaluates all four with
+// compile-time constants.
 // ---------------------------------------------------------------------------
+template <int IP>
+struct Basis;
+template <>
+struct Basis<0> {                      // GD p = 3, coefficients of s^0..s^5
+    static constexpr int DEG = 5;
+    static constexpr double c[4][6] = {
+        {0.0, -0.5, 11.0 / 12.0, -1.0 / 6.0, -5.0 / 12.0, 1.0 / 6.0},
+        {1.0, 0.0, -2.25, 0.5, 1.25, -0.5},
+        {0.0, 0.5, 1.75, -0.5, -1.25, 0.5},
+        {0.0, 0.0, -5.0 / 12.0, 1.0 / 6.0, 5.0 / 12.0, -1.0 / 6.0}};
+};
+template <>
+struct Basis<1> {                      // Catmull-Rom, coefficients of t^0..t^3
+    static constexpr int DEG = 3;
+    static constexpr double c[4][6] = {
+        {0.0, -0.5, 1.0, -0.5, 0.0, 0.0},
+        {1.0, 0.0, -2.5, 1.5, 0.0, 0.0},
+        {0.0, 0.5, 2.0, -1.5, 0.0, 0.0},
+        {0.0, 0.0, -0.5, 0.5, 0.0, 0.0}};
+};
+
+// Monomial coefficients of one node's weight and derivative, as values (a
+// lane keeps those of its own node offset in registers).
 template <typename T>
-__device__ __forceinline__ void gd_weights(T s, T w[4], T dw[4])
+struct Piece {
+    T c[6];   // w  = sum c[k] s^k
+    T d[5];   // w' = sum d[k] s^k, d[k] = (k + 1) c[k + 1]
+};
+
+template <typename T, int IP>
+__device__ __forceinline__ Piece<T> piece(int a)
 {
-    const T c12 = T(1.0 / 12.0), c6 = T(1.0 / 6.0);
-    const T s2 = s * s;
-    w[0] = s * fm(s, fm(s, fm(s, fm(s, c6, T(-5) * c12), -c6), T(11) * c12), T(-0.5));
-    w[1] = fm(s2, fm(s, fm(s, fm(s, T(-0.5), T(1.25)), T(0.5)), T(-2.25)), T(1));
-    w[2] = s * fm(s, fm(s, fm(s, fm(s, T(0.5), T(-1.25)), T(-0.5)), T(1.75)), T(0.5));
-    w[3] = s2 * fm(s, fm(s, fm(s, -c6, T(5) * c12), c6), T(-5) * c12);
-    dw[0] = fm(s, fm(s, fm(s, fm(s, T(5) * c6, T(-5) / T(3)), T(-0.5)), T(11) * c6), T(-0.5));
-    dw[1] = s * fm(s, fm(s, fm(s, T(-2.5), T(5)), T(1.5)), T(-4.5));
-    dw[2] = fm(s, fm(s, fm(s, fm(s, T(2.5), T(-5)), T(-1.5)), T(3.5)), T(0.5));
-    dw[3] = s * fm(s, fm(s, fm(s, T(-5) * c6, T(5) / T(3)), T(0.5)), T(-5) * c6);
+    Piece<T> p;
+#pragma unroll
+    for (int k = 0; k <= Basis<IP>::DEG; ++k) {
+        double v = a == 0 ? Basis<IP>::c[0][k] : a == 1 ? Basis<IP>::c[1][k]
+                 : a == 2 ? Basis<IP>::c[2][k] : Basis<IP>::c[3][k];
+        p.c[k] = T(v);
+    }
+#pragma unroll
+    for (int k = 0; k < Basis<IP>::DEG; ++k) {
+        double v = a == 0 ? Basis<IP>::c[0][k + 1] : a == 1 ? Basis<IP>::c[1][k + 1]
+                 : a == 2 ? Basis<IP>::c[2][k + 1] : Basis<IP>::c[3][k + 1];
+        p.d[k] = T(v * double(k + 1));
+    }
+    return p;
 }
 
-// Catmull-Rom cubic weights (eq. cr_basis), the paper's comparison scheme.
-template <typename T>
-__device__ __forceinline__ void cr_weights(T t, T w[4], T dw[4])
+template <typename T, int IP>
+__device__ __forceinline__ void eval_piece(const Piece<T> &p, T s, T &w, T &dw)
 {
-    w[0] = T(0.5) * t * fm(t, T(2) - t, T(-1));
-    w[1] = T(0.5) * fm(t * t, fm(T(3), t, T(-5)), T(2));
-    w[2] = T(0.5) * t * fm(t, fm(T(-3), t, T(4)), T(1));
-    w[3] = T(0.5) * t * t * (t - T(1));
-    dw[0] = T(0.5) * fm(t, fm(T(-3), t, T(4)), T(-1));
-    dw[1] = T(0.5) * t * fm(T(9), t, T(-10));
-    dw[2] = T(0.5) * fm(t, fm(T(-9), t, T(8)), T(1));
-    dw[3] = T(0.5) * t * fm(T(3), t, T(-2));
+    constexpr int D = Basis<IP>::DEG;
+    T x = p.c[D];
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) x = fm(x, s, p.c[k]);
+    T y = p.d[D - 1];
+#pragma unroll
+    for (int k = D - 2; k >= 0; --k) y = fm(y, s, p.d[k]);
+    w = x;
+    dw = y;
 }
 
-// Weight and derivative of one node offset (a = 0..3 for offsets -1..2).
-template <typename T>
-__device__ __forceinline__ void gd_weight1(T s, int a, T &w, T &dw)
+// All four weights of one axis with compile-time coefficients.
+template <typename T, int IP>
+__device__ __forceinline__ void weights4(T s, T w[4], T dw[4])
 {
-    T w4[4], d4[4];
-    gd_weights<T>(s, w4, d4);
-    w = a == 0 ? w4[0] : a == 1 ? w4[1] : a == 2 ? w4[2] : w4[3];
-    dw = a == 0 ? d4[0] : a == 1 ? d4[1] : a == 2 ? d4[2] : d4[3];
-}
-
-template <typename T>
-__device__ __forceinline__ void cr_weight1(T s, int a, T &w, T &dw)
-{
-    T w4[4], d4[4];
-    cr_weights<T>(s, w4, d4);
-    w = a == 0 ? w4[0] : a == 1 ? w4[1] : a == 2 ? w4[2] : w4[3];
-    dw = a == 0 ? d4[0] : a == 1 ? d4[1] : a == 2 ? d4[2] : d4[3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) eval_piece<T, IP>(piece<T, IP>(a), s, w[a], dw[a]);
 }
 
 // Cell of one axis: t in index units, cell k = clamp(floor(t), 1, n-3),
@@ -118,22 +145,30 @@ __device__ __forceinline__ int locate(double t, int n, double &s)
     return int(f);
 }
 
-// Reciprocal by Newton-Raphson: the hardware estimate refined twice
-// (each step x' = x + x (1 - a x) doubles the correct bits), ~1 ulp.
+// Reciprocal and reciprocal square root from the hardware estimates.  On
+// gfx950 v_rcp_f64 / v_rsq_f64 are good to about 24 bits (max relative error
+// 4.6e-8 / 5.2e-8 measured over 2^20 arguments), so one Newton step for the
+// reciprocal (x' = x + x (1 - a x), error ~ e^2 ~ 2e-15) and two for the
+// reciprocal square root (x' = x + x (1/2 - (a/2) x^2)) bring them to
+// FP64 working accuracy.  The FP32 estimates are within 1.5 ulp of FP32
+// (9.0e-8 / 9.3e-8) and are used as they are.
 __device__ __forceinline__ double rcp(double a)
 {
     double x = __builtin_amdgcn_rcp(a);
     double e = fma(-a, x, 1.0);
-    x = fma(x, e, x);
-    e = fma(-a, x, 1.0);
     return fma(x, e, x);
 }
-__device__ __forceinline__ float rcp(float a)
+__device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ double rsqrt(double a)
 {
-    float x = __builtin_amdgcn_rcpf(a);
-    float e = fmaf(-a, x, 1.0f);
-    return fmaf(x, e, x);
+    const double h = 0.5 * a;
+    double x = __builtin_amdgcn_rsq(a);
+    double e = fma(-h, x * x, 0.5);
+    x = fma(x, e, x);
+    e = fma(-h, x * x, 0.5);
+    return fma(x, e, x);
 }
+__device__ __forceinline__ float rsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
 
 // sin and cos of theta0 + d from those of theta0, for a small increment d
 // (|d| <= 0.05 rad): Taylor series of sin d and cos d (error < d^9/9!) and
@@ -148,23 +183,23 @@ __device__ __forceinline__ void sincos_add(double s0, double c0, double d, doubl
     c = fm(c0, cd, -(s0 * sd));
 }
 
-// Height-then-longitude contraction of one latitude row of the stencil
-// (4 columns x 4 heights): s0 = value, s1 = d/dlon, s2 = d/dh, each still to
-// be weighted by the latitude weight of the row.
-// Exchange with the lane (lane ^ 1) or (lane ^ 2) of the same quad through
-// a DPP quad permutation (no LDS round trip).
+// Cross-lane exchange through DPP (no LDS round trip), on the two 32-bit
+// halves of a double: quad permutations within groups of 4 lanes and the
+// 16-lane row mirrors.
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true); }
 template <int CTRL>
-__device__ __forceinline__ double quad_swap(double v)
+__device__ __forceinline__ double dpp(double v)
 {
     int lo = dpp_i<CTRL>(__double2loint(v)), hi = dpp_i<CTRL>(__double2hiint(v));
     return __hiloint2double(hi, lo);
 }
 template <int CTRL>
-__device__ __forceinline__ float quad_swap(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
-constexpr int kQuadXor1 = 0xB1;   // quad_perm(1, 0, 3, 2)
-constexpr int kQuadXor2 = 0x4E;   // quad_perm(2, 3, 0, 1)
+__device__ __forceinline__ float dpp(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
+constexpr int kQuadXor1 = 0xB1;          // quad_perm(1, 0, 3, 2): lane ^ 1
+constexpr int kQuadXor2 = 0x4E;          // quad_perm(2, 3, 0, 1): lane ^ 2
+constexpr int kRowMirror = 0x140;        // lane i <- lane 15 - i within 16
+constexpr int kRowHalfMirror = 0x141;    // lane i <- lane 7 - i within 8
 
 // The grid lives in global memory; saying so (address space 1) lets the
 // compiler use global loads, which do not share a wait counter with the
@@ -172,62 +207,56 @@ constexpr int kQuadXor2 = 0x4E;   // quad_perm(2, 3, 0, 1)
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T *;
 
-// Load one latitude row of the stencil: 4 columns x 4 consecutive heights.
+// Load one column of the stencil: 4 consecutive heights.
 template <typename T>
-__device__ __forceinline__ void row_load(gptr<T> p, size_t nh, T u[16])
+__device__ __forceinline__ void col_load(gptr<T> p, T u[4])
 {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        gptr<T> q = p + size_t(b) * nh;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) u[4 * b + c] = q[c];
-    }
+    for (int c = 0; c < 4; ++c) u[c] = p[c];
 }
 
-// Height-then-longitude contraction of one loaded latitude row: s0 = value,
-// s1 = d/dlon, s2 = d/dh, each still to be weighted by the row's latitude
-// weight.
+// Contraction order, shared by every kernel variant so that all give the
+// same rounded result: per column, heights in a fused chain (value and
+// d/dh); per latitude row, the four weighted columns as
+// (col0 + col1) + (col2 + col3); over rows, (row0 + row3) + (row1 + row2).
 template <typename T>
-__device__ __forceinline__ void row_contract(const T u[16], const T wh[4], const T dwh[4],
-                                             const T wo[4], const T dwo[4], T &s0, T &s1, T &s2)
+__device__ __forceinline__ void col_contract(const T u[4], const T wh[4], const T dwh[4], T &cv, T &dcv)
 {
-    s0 = s1 = s2 = T(0);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const T *q = u + 4 * b;
-        T c0 = fm(q[3], wh[3], fm(q[2], wh[2], fm(q[1], wh[1], q[0] * wh[0])));
-        T c1 = fm(q[3], dwh[3], fm(q[2], dwh[2], fm(q[1], dwh[1], q[0] * dwh[0])));
-        s0 = fm(c0, wo[b], s0);
-        s1 = fm(c0, dwo[b], s1);
-        s2 = fm(c1, wo[b], s2);
-    }
+    cv = fm(u[3], wh[3], fm(u[2], wh[2], fm(u[1], wh[1], u[0] * wh[0])));
+    dcv = fm(u[3], dwh[3], fm(u[2], dwh[2], fm(u[1], dwh[1], u[0] * dwh[0])));
 }
 
 // The stencil values a lane last loaded and the cell they belong to.  Rays
 // move less than a cell per RK4 stage, so most evaluations reuse them and
 // skip the gather (and its memory round trip).  il < 0: empty.
+//   LANES = 1:  the lane holds all 4 x 4 x 4 nodes, u[a][b][c].
+//   LANES = 16: each lane of a 16-lane row holds one column (lat offset
+//               a = (lane >> 2) & 3, lon offset b = lane & 3), u[0][0][c],
+//               and the coefficients of its own lat and lon weights.
 template <typename T, int LANES>
 struct StencilCache {
-    static constexpr int ROWS = (LANES == 1) ? 4 : 1;
+    static constexpr int NA = (LANES == 1) ? 4 : 1;
     int il, jl, kh;
-    T u[ROWS][16];
+    T u[NA][NA][4];
+    T uref;                   // node (1, 1, 1), the mixed path's reference
+    Piece<T> pa, pb;          // LANES = 16: weights of this lane's a and b
     __device__ void clear() { il = -1; jl = -1; kh = -1; }
 };
 
 // f_N^2 (MHz^2, returned in FP64) and its partials d/dr, d/dtheta, d/dphi
-// at a position.
-// Below the grid bottom the medium is vacuum; outside the box laterally or
-// above the top the value is continued as a constant.
+// at a position.  Below the grid bottom the medium is vacuum; outside the
+// box laterally or above the top the value is continued as a constant.
 //
-// LANES = 1: one lane does the whole 4x4x4 stencil.  LANES = 4: the four
-// lanes of a quad each take one latitude row and the row results are
-// combined across the quad.  Both combine the four weighted row results in
-// the same order, ((row0 + row1) + (row2 + row3)), with the products
-// rounded separately, so the two give bit-identical results.
+// LANES = 1: one lane does the whole 4x4x4 stencil.  LANES = 16: the 16
+// lanes of a row each contract one column; the row sums are formed within
+// quads and the lat sum across the row with DPP, in the order described at
+// col_contract, so the two variants give bit-identical results and every
+// lane of the row ends with the same values.
 template <typename T, int IP, int LANES>
 __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, double r, double th, double ph,
                                        StencilCache<T, LANES> &sc, double &F, T &Fr, T &Fth, T &Fph)
 {
+    static_assert(LANES == 1 || LANES == 16, "LANES must be 1 or 16");
     double h = r - g.R;
     if (h < g.h0) {
         F = 0.0;
@@ -256,11 +285,18 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
     // before any use, so that the memory round trips overlap (one wait
     // instead of one per column); the weights are computed while the loads
     // are in flight.
-    constexpr int ROWS = StencilCache<T, LANES>::ROWS;
-    const int a0 = (LANES == 1) ? 0 : (int(__lane_id()) & 3);
+    const int lane = int(__lane_id());
+    const int a16 = (lane >> 2) & 3, b16 = lane & 3;
     if (il != sc.il || jl != sc.jl || kh != sc.kh) {
+        if constexpr (LANES == 1) {
 #pragma unroll
-        for (int k = 0; k < ROWS; ++k) row_load<T>(base + size_t(a0 + k) * row, nh, sc.u[k]);
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) col_load<T>(base + size_t(a) * row + size_t(b) * nh, sc.u[a][b]);
+        } else {
+            col_load<T>(base + size_t(a16) * row + size_t(b16) * nh, sc.u[0][0]);
+            if constexpr (sizeof(T) == 4) sc.uref = base[row + nh + 1];
+        }
         sc.il = il;
         sc.jl = jl;
         sc.kh = kh;
@@ -268,71 +304,77 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
     __builtin_amdgcn_sched_barrier(0);
 
     // FP32 (mixed path): contract the differences u - u_ref to the cell's
-    // base node.  The weights sum to 1 and their derivatives to 0, so this is
-    // the same interpolant, but the gradient no longer cancels between large
-    // node values where the density varies little across the cell.
-    T u[ROWS][16];
+    // node (1, 1, 1).  The weights sum to 1 and their derivatives to 0, so
+    // this is the same interpolant, but the gradient no longer cancels
+    // between large node values where the density varies little across the
+    // cell.
     T uref = T(0);
-    if constexpr (sizeof(T) == 4) {
-        if constexpr (LANES == 1) {
-            uref = sc.u[1][4 * 1 + 1];               // node (a, b, c) = (1, 1, 1)
-        } else {
-            uref = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sc.u[0][4 * 1 + 1]),
-                                                              0x55, 0xF, 0xF, true));  // from lane a = 1
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < ROWS; ++k)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) u[k][j] = sc.u[k][j] - uref;
+    if constexpr (sizeof(T) == 4) uref = (LANES == 1) ? sc.u[1][1][1] : sc.uref;
 
-    // IP = 0: Galerkin-Difference p = 3 (the method); IP = 1: Catmull-Rom
-    T wo[4], dwo[4], wh[4], dwh[4];
-    if constexpr (IP == 1) {
-        cr_weights<T>(T(so_), wo, dwo);
-        cr_weights<T>(T(sh_), wh, dwh);
-    } else {
-        gd_weights<T>(T(so_), wo, dwo);
-        gd_weights<T>(T(sh_), wh, dwh);
-    }
+    T wh[4], dwh[4];
+    weights4<T, IP>(T(sh_), wh, dwh);
 
     T v, glat, glon, gh;
     if constexpr (LANES == 1) {
-        T wl[4], dwl[4];
-        if constexpr (IP == 1) cr_weights<T>(T(sl_), wl, dwl);
-        else gd_weights<T>(T(sl_), wl, dwl);
+        T wo[4], dwo[4], wl[4], dwl[4];
+        weights4<T, IP>(T(so_), wo, dwo);
+        weights4<T, IP>(T(sl_), wl, dwl);
         T pv[4], pla[4], plo[4], phh[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            T s0, s1, s2;
-            row_contract<T>(u[a], wh, dwh, wo, dwo, s0, s1, s2);
+            T t0[4], t1[4], t2[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                T uu[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) uu[c] = sc.u[a][b][c] - uref;
+                T cv, dcv;
+                col_contract<T>(uu, wh, dwh, cv, dcv);
+                t0[b] = cv * wo[b];
+                t1[b] = cv * dwo[b];
+                t2[b] = dcv * wo[b];
+            }
+            const T s0 = (t0[0] + t0[1]) + (t0[2] + t0[3]);
+            const T s1 = (t1[0] + t1[1]) + (t1[2] + t1[3]);
+            const T s2 = (t2[0] + t2[1]) + (t2[2] + t2[3]);
             pv[a] = s0 * wl[a];
             pla[a] = s0 * dwl[a];
             plo[a] = s1 * wl[a];
             phh[a] = s2 * wl[a];
         }
-        v = (pv[0] + pv[1]) + (pv[2] + pv[3]);
-        glat = (pla[0] + pla[1]) + (pla[2] + pla[3]);
-        glon = (plo[0] + plo[1]) + (plo[2] + plo[3]);
-        gh = (phh[0] + phh[1]) + (phh[2] + phh[3]);
+        v = (pv[0] + pv[3]) + (pv[1] + pv[2]);
+        glat = (pla[0] + pla[3]) + (pla[1] + pla[2]);
+        glon = (plo[0] + plo[3]) + (plo[1] + plo[2]);
+        gh = (phh[0] + phh[3]) + (phh[1] + phh[2]);
     } else {
-        static_assert(LANES == 4, "LANES must be 1 or 4");
-        const int a = a0;
-        T s0, s1, s2, wl, dwl;
-        row_contract<T>(u[0], wh, dwh, wo, dwo, s0, s1, s2);
-        if constexpr (IP == 1) cr_weight1<T>(T(sl_), a, wl, dwl);
-        else gd_weight1<T>(T(sl_), a, wl, dwl);
+        T wo, dwo, wl, dwl;
+        eval_piece<T, IP>(sc.pb, T(so_), wo, dwo);
+        eval_piece<T, IP>(sc.pa, T(sl_), wl, dwl);
+        T uu[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) uu[c] = sc.u[0][0][c] - uref;
+        T cv, dcv;
+        col_contract<T>(uu, wh, dwh, cv, dcv);
+        T t0 = cv * wo, t1 = cv * dwo, t2 = dcv * wo;
+        // within the quad (lon offsets b): lanes b, b^1 form t_b + t_b^1,
+        // then (t0 + t1) + (t2 + t3) -- equal on all four lanes
+        t0 = t0 + dpp<kQuadXor1>(t0);
+        t1 = t1 + dpp<kQuadXor1>(t1);
+        t2 = t2 + dpp<kQuadXor1>(t2);
+        const T s0 = t0 + dpp<kQuadXor2>(t0);
+        const T s1 = t1 + dpp<kQuadXor2>(t1);
+        const T s2 = t2 + dpp<kQuadXor2>(t2);
         T pv = s0 * wl, pla = s0 * dwl, plo = s1 * wl, phh = s2 * wl;
-        // (row a + row a^1), then + the other pair: lanes 0,1 form
-        // (p0+p1)+(p2+p3), lanes 2,3 (p2+p3)+(p0+p1) -- equal, + commutes
-        pv = pv + quad_swap<kQuadXor1>(pv);
-        pla = pla + quad_swap<kQuadXor1>(pla);
-        plo = plo + quad_swap<kQuadXor1>(plo);
-        phh = phh + quad_swap<kQuadXor1>(phh);
-        v = pv + quad_swap<kQuadXor2>(pv);
-        glat = pla + quad_swap<kQuadXor2>(pla);
-        glon = plo + quad_swap<kQuadXor2>(plo);
-        gh = phh + quad_swap<kQuadXor2>(phh);
+        // across the row (lat offsets a): mirror pairs a with 3 - a, the half
+        // mirror then pairs (a, 3 - a) with (1 - a, 2 + a)
+        pv = pv + dpp<kRowMirror>(pv);
+        pla = pla + dpp<kRowMirror>(pla);
+        plo = plo + dpp<kRowMirror>(plo);
+        phh = phh + dpp<kRowMirror>(phh);
+        v = pv + dpp<kRowHalfMirror>(pv);
+        glat = pla + dpp<kRowHalfMirror>(pla);
+        glon = plo + dpp<kRowHalfMirror>(plo);
+        gh = phh + dpp<kRowHalfMirror>(phh);
     }
     // index space -> physical: t_h = (r - R - h0)/dh,
     // t_lat = (90 - theta deg - lat0)/dlat, t_lon = (phi deg - lon0)/dlon
@@ -354,8 +396,9 @@ template <typename T>
 __device__ __forceinline__ void appleton_partials(T X, T u, T a, T b, int sigma, T &mX, T &ma, T &mb)
 {
     T bu = b * u;
-    T S = sqrt(fm(a, a, T(4) * bu * u));
-    T iS = rcp(S);
+    const T S2 = fm(a, a, T(4) * bu * u);
+    const T iS = rsqrt(S2);
+    const T S = S2 * iS;
     T Tt = S + a;
     if (sigma > 0) {
         T iT = rcp(Tt);

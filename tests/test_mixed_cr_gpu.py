@@ -133,7 +133,7 @@ def test_mixed_tail_kernel_bit_identical_to_one_lane(rt, ctx):
     fan = synth.sub_fan(wl.fan, elev_idx=[0, 9, 21, 40, 63], az_idx=[0, 7, 13, 22, 31, 50, 63])
     grid = rt.Grid(ctx, wl.grid)
     one = gpu_trace(rt, ctx, grid, wl, fan, precision="mixed", tail_threshold=-1)
-    four = gpu_trace(rt, ctx, grid, wl, fan, precision="mixed", tail_threshold=1 << 20)
+    tail = gpu_trace(rt, ctx, grid, wl, fan, precision="mixed", tail_threshold=1 << 20)
     grid.close()
     for k in ("group_km", "range_km", "az_dev_deg", "status", "n_steps"):
-        assert np.array_equal(one[k], four[k], equal_nan=True), k
+        assert np.array_equal(one[k], tail[k], equal_nan=True), k

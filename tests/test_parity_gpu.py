@@ -231,17 +231,28 @@ def test_grid_create_rejects_bad_values(rt, ctx):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_four_lane_tail_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
-    """The four-lanes-per-ray tail kernel splits only the stencil contraction
-    and combines it in the one-lane order: outputs are identical whether a
-    ray finishes in the one-lane kernel (hand-off off) or runs entirely in
-    the tail kernel (threshold above the ray count)."""
+def test_tail_kernel_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
+    """The sixteen-lanes-per-ray tail kernel splits only the stencil
+    contraction and combines it in the one-lane order: outputs are
+    identical whether a ray finishes in the one-lane kernel (hand-off off),
+    runs entirely in the tail kernel (threshold above the ray count, so
+    every ray is handed off at the first check) or is handed off midway."""
     fan = _subfan(aniso_wl)
     one = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=-1)
-    four = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision,
+    tail = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision,
                      tail_threshold=1 << 20)
     mid = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=100)
     for k in ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "status", "n_steps"):
-        assert np.array_equal(one[k], four[k], equal_nan=True), k
+        assert np.array_equal(one[k], tail[k], equal_nan=True), k
         assert np.array_equal(one[k], mid[k], equal_nan=True), k
-    assert one["total_steps"] == four["total_steps"] == mid["total_steps"]
+    assert one["total_steps"] == tail["total_steps"] == mid["total_steps"]
+
+
+def test_single_ray_is_handed_off(rt, ctx, aniso_wl, aniso_grid):
+    """A lone ray with the hand-off on runs in the tail kernel (at most
+    `threshold` live rays) and still equals the one-lane result."""
+    fan = synth.sub_fan(aniso_wl.fan, elev_idx=[30], az_idx=[10], freq_idx=[1])
+    a = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, tail_threshold=-1)
+    b = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, tail_threshold=1)
+    for k in ("group_km", "range_km", "az_dev_deg", "status", "n_steps"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
