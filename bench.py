@@ -70,7 +70,8 @@ def parse():
 
 def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup, tune=None):
     out = None
-    kw = dict(tail_threshold=tune["tail_threshold"], waves_per_simd=tune["waves_per_simd"]) if tune else {}
+    kw = dict(tail_threshold=tune["tail_threshold"], waves_per_simd=tune["waves_per_simd"],
+              ray_order=tune["ray_order"]) if tune else {}
     for _ in range(warmup):
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
                          exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out, **kw)
@@ -119,7 +120,7 @@ def main():
         from paper_2506_18579_amd import serve
         snaps = [rtgd.Grid(ctx, synth.ionosphere_grid(synth.GEOM_ANISO, s)) for s in range(4)]
         reqs = synth.serving_requests(a.serve_requests, seed=1234, n_snapshots=4, max_rays=20000,
-                                      qps=a.serve_qps)
+                                      qps=a.serve_qps, ionogram_fraction=0.1)
         sopts = dict(step_km=1.0, max_group_km=4000.0, exit_h_km=600.0)
         burst = [dict(q, t_arrive=0.0) for q in reqs]
 
@@ -267,8 +268,10 @@ def main():
             "fp64_latency_ms_p99": float(np.percentile(lat, 99)),
             "mixed_latency_ms_p50": float(np.percentile(lat32, 50)),
             "mixed_latency_ms_p99": float(np.percentile(lat32, 99))},
-        "serving": dict(serving, workload=f"{a.serve_requests} fans of 1-20,000 rays "
-                        "(log-uniform), 4 resident 181x181x226 snapshots, 4 slots, 256 MiB output "
+        "serving": dict(serving, workload=f"{a.serve_requests} requests, 90 % ray fans of "
+                        "1-20,000 rays (log-uniform) and 10 % ionogram syntheses (500-4,000-ray "
+                        "sweeps of the 1200 km link), 4 resident 181x181x226 snapshots, 4 slots, "
+                        "256 MiB output "
                         "arena; all requests at once (saturation), then Poisson arrivals at 25, "
                         "50 and 90 % of the saturation request rate") if serving else None,
     }

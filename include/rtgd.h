@@ -114,14 +114,25 @@ typedef struct {
     int32_t traj_stride;    /* record every traj_stride-th step; 0 = none  */
     int64_t traj_capacity;  /* records available in rt_results.traj        */
     int32_t results_mem;    /* RT_MEM_HOST or RT_MEM_DEVICE                */
-    int32_t tail_threshold; /* scheduling knob, results unchanged: once the
-                               queue is empty and at most this many rays are
-                               live, each is finished by 16 lanes instead
-                               of one; 0 = library default, < 0 = never   */
+    int32_t tail_threshold; /* scheduling knob, results unchanged.  Rays
+                               start one lane each; once the queue is empty:
+                               > 0: once at most this many rays are live in
+                               the launch, all are handed to a separate
+                               16-lanes-per-ray tail kernel;
+                               0: the same at 16 rays per CU (default);
+                               -1: one lane per ray throughout;
+                               -2: a wave left with <= 4 live rays
+                               finishes them 16 lanes per ray itself      */
     int32_t waves_per_simd; /* scheduling knob, results unchanged: register
                                budget of the kernels, 1 = whole register
                                file, 2 = two waves per SIMD; 0 = default  */
-    int32_t reserved;       /* must be 0                                   */
+    int32_t ray_order;      /* scheduling knob, results unchanged: order in
+                               which waves take rays from the queue; 0 =
+                               default (index order), 1 = index order,
+                               2 = strided: q -> q * s mod n_rays with s
+                               coprime to n_rays near 0.618 n_rays, which
+                               spreads neighbouring (similar) rays over
+                               many waves                                  */
 } rt_trace_opts;
 
 /* Per-ray outputs, arrays of N_r = rt_fan_count() elements, owned by the
@@ -193,7 +204,8 @@ rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
  * out[(t * max_points + k) * 4 + {0,1,2,3}] = elevation (deg), group path
  * (km), phase path (km), apogee (km) of the k-th crossing of trace
  * t = i_freq * n_mode + i_mode, in increasing elevation; counts[t] = number
- * of crossings found (may exceed max_points; only max_points are written).
+ * of crossings found (may exceed max_points; only max_points are kept).
+ * Slots k >= counts[t] of a trace are set to 0.
  * res arrays group_km, phase_km, range_km, apogee_km and status are read;
  * mem (RT_MEM_HOST / RT_MEM_DEVICE) says where res, out and counts live.
  * RT_E_INVALID on a fan that is not a sweep or missing arrays. */
@@ -285,13 +297,12 @@ rt_status rt_plan_wait(rt_plan *plan, int64_t *total_steps, double *kernel_ms);
 void rt_plan_destroy(rt_plan *plan);
 
 /* ------------------------------------------------------------------------
- * Autotuner.  The launch settings that change speed but not results are the
- * hand-off threshold of the 16-lane tail kernel (tail_threshold) and the
- * register budget of the one-lane kernel (waves_per_simd).  rt_autotune
- * traces the given fan once per candidate setting (tail_threshold in
- * {off, 8, 16, 32 rays per CU} x waves_per_simd in {1, 2}), keeps the
- * fastest by device time and writes base with those two fields replaced to
- * *tuned.  Choices are cached in the process under a key made of the
+ * Autotuner.  The launch settings that change speed but not results are
+ * tail_threshold, waves_per_simd and ray_order (see rt_trace_opts).
+ * rt_autotune traces the given fan once per candidate setting
+ * (tail_threshold in {-2, -1, 8 and 16 rays per CU} x waves_per_simd
+ * in {1, 2} x ray_order in {index, strided}), keeps the fastest by device
+ * time and writes base with those three fields replaced to *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on
  * or off and the ray count rounded to a power of two; a cached key is
  * answered without tracing.  Results of the trial traces are discarded

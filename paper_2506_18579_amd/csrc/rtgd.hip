@@ -80,6 +80,8 @@ struct TraceParams {
     struct Handoff *handoff;   // capacity handoff_threshold
     int32_t handoff_threshold; // hand off once at most this many rays are live (0: never);
                                // also the hand-off buffer capacity
+    int32_t inwave;            // a drained wave with <= 4 live rays finishes them 16 lanes each
+    int64_t perm_stride;       // launch ray q is visited as (q * perm_stride) mod n_rays
 };
 
 // State of a ray moved from the one-lane to the sixteen-lane kernel.
@@ -334,19 +336,86 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred, int lane
     return base + __popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// Sixteen lanes (a DPP row) per ray until every ray of the wave has
+// terminated; rows with ray < 0 idle.  The row's lanes hold identical state
+// and run identical arithmetic; only the stencil contraction is split (one
+// column per lane, see medium<T, IP, 16>), so the results equal the
+// one-lane kernel's bit for bit.  Lane 0 of the row writes.
+template <typename T, int IP>
+__device__ __forceinline__ void run_rows(const TraceParams<T> &P, int ray, Lane &L)
+{
+    const int lane = int(__lane_id());
+    const bool lead = (lane & 15) == 0;
+    StencilCache<T, 16> sc;
+    sc.clear();
+    sc.pa = piece<T, IP>((lane >> 2) & 3);
+    sc.pb = piece<T, IP>(lane & 3);
+    for (;;) {
+        if (__ballot(ray >= 0) == 0ull) break;
+        if (ray >= 0) {
+            int st = advance<T, IP, 16>(P, ray, L, lead, sc);
+            if (st >= 0) {
+                if (lead) finish_ray(P, ray, L, st);
+                ray = -1;
+            }
+        }
+    }
+}
+
+// Move the (at most four) live rays of the wave, marked in `live`, onto
+// the wave's four 16-lane rows, in lane order; rows without a ray get -1.
+__device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, Lane &L)
+{
+    const int row = int(__lane_id()) >> 4;
+    int src = -1;
+    unsigned long long m = live;
+    for (int i = 0; i < 4 && m; ++i) {
+        const int b = __ffsll((long long)m) - 1;
+        if (i == row) src = b;
+        m &= m - 1ull;
+    }
+    const int s = src < 0 ? 0 : src;
+    Lane M;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) M.y[i] = __shfl(L.y[i], s);
+    M.gp = __shfl(L.gp, s);
+    M.apogee = __shfl(L.apogee, s);
+    M.az0 = __shfl(L.az0, s);
+    M.rc.v = reinterpret_cast<const void *>(
+        __shfl((unsigned long long)reinterpret_cast<uintptr_t>(L.rc.v), s));
+    M.rc.inv_f2 = __shfl(L.rc.inv_f2, s);
+    M.rc.Y0 = __shfl(L.rc.Y0, s);
+    M.rc.sigma = __shfl(L.rc.sigma, s);
+    M.steps = __shfl(L.steps, s);
+    M.ntraj = __shfl(L.ntraj, s);
+    M.seg = __shfl(L.seg, s);
+    M.local = __shfl(L.local, s);
+    const int r = __shfl(ray, s);
+    L = M;
+    ray = src < 0 ? -1 : r;
+}
+
 // Persistent one-lane-per-ray kernel.  Each 64-lane wave loops { refill
 // idle lanes from the queue; one RK4 step on every live lane } until the
-// queue is drained and every lane is idle.  When the queue is drained and
-// at most handoff_threshold rays are live, each remaining ray's state is
-// written to the hand-off buffer and the lane retires (the tail kernel
-// finishes it with sixteen lanes per ray).  Every ray terminates (the group
-// path grows by one step per iteration up to max_group), so every wave exits.
+// queue is drained and every lane is idle.  Rays are visited in the order
+// (q * perm_stride) mod n_rays, which spreads runs of neighbouring (and
+// similarly long) rays over many waves.  Once the queue is drained, either
+//   * (inwave) a wave left with at most four live rays moves them onto its
+//     four 16-lane rows and finishes them there, or
+//   * (handoff_threshold > 0) once at most handoff_threshold rays are live
+//     in the whole launch, each remaining ray's state is written to the
+//     hand-off buffer and the lane retires (the tail kernel finishes it with
+//     sixteen lanes per ray).
+// Every ray terminates (the group path grows by one step per iteration up
+// to max_group), so every wave exits.
 template <typename T, int IP>
 __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp)
 {
     const TraceParams<T> &P = *Pp;
     const int lane = int(__lane_id());
     int ray = -1;            // -1 idle, -2 queue drained, >= 0 live ray
+    bool drained = false;
+    unsigned long long to_rows = 0ull;   // live rays moving to 16-lane rows
     Lane L;
     StencilCache<T, 1> sc;
     sc.clear();
@@ -356,14 +425,21 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
             int q = wave_append(P.queue_head, need, lane);
             if (need) {
                 if (q < P.n_rays) {
-                    ray = q;
+                    ray = int((unsigned long long)q * (unsigned long long)P.perm_stride %
+                              (unsigned long long)P.n_rays);
                     init_ray(P, ray, L, true);
                 } else {
                     ray = -2;
                 }
             }
+            drained = drained || __ballot(ray == -2) != 0ull;
         }
-        if (__ballot(ray >= 0) == 0ull) break;
+        const unsigned long long livem = __ballot(ray >= 0);
+        if (livem == 0ull) break;
+        if (P.inwave && drained && __popcll(livem) <= 4) {
+            to_rows = livem;
+            break;
+        }
         if (P.handoff_threshold > 0 && (iter & 7) == 0) {
             int live = 0, head = 0;
             if (lane == 0) {
@@ -403,6 +479,11 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
         unsigned long long fin = __ballot(st >= 0);
         if (lane == 0 && fin && P.handoff_threshold > 0) atomicSub(P.live, __popcll(fin));
     }
+    // after the one-lane loop, so that its stencil cache is dead here
+    if (to_rows) {
+        gather_rows(to_rows, ray, L);
+        run_rows<T, IP>(P, ray, L);
+    }
 }
 
 // Tail kernel: sixteen lanes (a DPP row) per handed-off ray, four rays per
@@ -417,14 +498,9 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
     const TraceParams<T> &P = *Pp;
     const int lane = int(__lane_id());
     const int slot = int(blockIdx.x) * 4 + (lane >> 4);
-    const bool lead = (lane & 15) == 0;
     const int n = *P.n_handoff;
     int ray = -1;
     Lane L;
-    StencilCache<T, 16> sc;
-    sc.clear();
-    sc.pa = piece<T, IP>((lane >> 2) & 3);
-    sc.pb = piece<T, IP>(lane & 3);
     if (slot < n) {
         const Handoff &H = P.handoff[slot];
         ray = H.ray;
@@ -437,16 +513,7 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
         L.steps = H.steps;
         L.ntraj = H.ntraj;
     }
-    for (;;) {
-        if (__ballot(ray >= 0) == 0ull) break;
-        if (ray >= 0) {
-            int st = advance<T, IP, 16>(P, ray, L, lead, sc);
-            if (st >= 0) {
-                if (lead) finish_ray(P, ray, L, st);
-                ray = -1;
-            }
-        }
-    }
+    run_rows<T, IP>(P, ray, L);
 }
 
 // Oblique-ionogram extraction: one thread per (frequency, mode) trace scans
@@ -478,6 +545,11 @@ __global__ __launch_bounds__(64) void k_ionogram(const double *__restrict__ elev
             o[3] = fm(w, apogee[i1] - apogee[i0], apogee[i0]);
         }
         ++found;
+    }
+    // unused slots are defined (zero), never stale memory
+    for (int k = found; k < max_points; ++k) {
+        double *o = out + (size_t(t) * size_t(max_points) + size_t(k)) * 4;
+        o[0] = o[1] = o[2] = o[3] = 0.0;
     }
     counts[t] = found;
 }
@@ -798,7 +870,9 @@ struct TraceJob {
     std::vector<JobSeg> segs;
     rt_trace_opts opts{};
     int n_rays = 0;
-    int tail = 0;              // hand-off threshold actually used
+    int tail = 0;              // launch-wide hand-off threshold actually used (0: none)
+    int inwave = 0;            // in-wave switch to 16 lanes per ray
+    int64_t perm = 1;          // visiting stride
     int occ = 1;               // register budget variant
     int32_t *tcount = nullptr;
     double *traj = nullptr;
@@ -857,10 +931,12 @@ rt_status validate_request(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
         return fail(ctx, RT_E_INVALID, "precision must be RT_FP64 or RT_MIXED");
     if (opts->results_mem != RT_MEM_HOST && opts->results_mem != RT_MEM_DEVICE)
         return fail(ctx, RT_E_INVALID, "results_mem must be RT_MEM_HOST or RT_MEM_DEVICE");
-    if (opts->tail_threshold > (1 << 24))
-        return fail(ctx, RT_E_INVALID, "tail_threshold too large");
+    if (opts->tail_threshold > (1 << 24) || opts->tail_threshold < -2)
+        return fail(ctx, RT_E_INVALID, "tail_threshold must be in [-2, 2^24]");
     if (opts->waves_per_simd < 0 || opts->waves_per_simd > 2)
         return fail(ctx, RT_E_INVALID, "waves_per_simd must be 0, 1 or 2");
+    if (opts->ray_order < 0 || opts->ray_order > 2)
+        return fail(ctx, RT_E_INVALID, "ray_order must be 0, 1 or 2");
     if (opts->traj_stride < 0 || opts->traj_capacity < 0)
         return fail(ctx, RT_E_INVALID, "negative trajectory option");
     if (!(fan->tx_h_km >= 0.0) || !(fan->tx_h_km < gq.h0_km))
@@ -886,6 +962,19 @@ rt_status validate_request(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
     return RT_OK;
 }
 
+// Stride of the visiting order q -> q s mod n: the first integer at or
+// above 0.618 n that is coprime to n (so the map is a permutation).
+int64_t visit_stride(int64_t n)
+{
+    if (n <= 2) return 1;
+    int64_t s = int64_t(0.6180339887498949 * double(n));
+    for (;; ++s) {
+        int64_t a = s, b = n;
+        while (b) { int64_t t = a % b; a = b; b = t; }
+        if (a == 1) return s;
+    }
+}
+
 // Launch-wide settings from the options and the total ray count.
 void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
 {
@@ -894,10 +983,10 @@ void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
     for (const JobSeg &s : job.segs) n64 += s.n_rays;
     job.n_rays = int(n64);
     job.occ = opts.waves_per_simd == 0 ? 1 : opts.waves_per_simd;
-    int tail = opts.tail_threshold;
-    if (tail == 0) tail = ctx->n_cu * 16;     // library default: 4 SIMDs x 4 rays per wave per CU
-    if (tail < 0) tail = 0;                   // hand-off off
-    job.tail = int(std::min<int64_t>(tail, n64));
+    const int tail = opts.tail_threshold == 0 ? ctx->n_cu * 16 : opts.tail_threshold;
+    job.inwave = tail == -2 ? 1 : 0;
+    job.tail = tail > 0 ? int(std::min<int64_t>(tail, n64)) : 0;
+    job.perm = opts.ray_order == 2 ? visit_stride(n64) : 1;
     job.per_ray = opts.traj_stride > 0 && n64 > 0 ? opts.traj_capacity / n64 : 0;
 }
 
@@ -913,6 +1002,7 @@ bool compatible(const JobSeg &a, const rt_trace_opts &oa, const JobSeg &b, const
            oa.step_km == ob.step_km && oa.max_group_km == ob.max_group_km &&
            oa.exit_h_km == ob.exit_h_km && oa.precision == ob.precision &&
            oa.tail_threshold == ob.tail_threshold && oa.waves_per_simd == ob.waves_per_simd &&
+           oa.ray_order == ob.ray_order &&
            oa.traj_stride == 0 && ob.traj_stride == 0;
 }
 
@@ -950,6 +1040,8 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.n_handoff = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, n_handoff));
     P.handoff = reinterpret_cast<Handoff *>(dev + lay.hand);
     P.handoff_threshold = job.tail;
+    P.inwave = job.inwave;
+    P.perm_stride = job.perm;
 }
 
 // Enqueue one launch on `stream`: stage fan axes, segment table, parameter
@@ -1317,11 +1409,13 @@ rt_status slot_reserve(rt_ctx *ctx, Slot &sl, size_t dev_bytes, size_t host_byte
     return RT_OK;
 }
 
-// Continuous batching: while a slot is idle, take from the head of the FIFO
-// queue every request that shares the head's geometry, transmitter and
-// options and whose outputs fit in the arena (up to the batch limits), and
-// launch them together on that slot's stream.  The head request waits, and
-// so does everything behind it, until the arena can hold its outputs.
+// Continuous batching: while a slot is idle, take the head of the FIFO queue
+// and, in queue order, every later request that shares the head's
+// geometry, transmitter and options (others are passed over and wait for a
+// launch of their own), as long as their outputs fit in the arena and the
+// batch limits hold; launch them together on that slot's stream.  The
+// first request whose outputs do not fit stops the batch, and the head
+// waits until the arena can hold its outputs.
 rt_status schedule(rt_server *srv)
 {
     while (!srv->queue.empty()) {
@@ -1335,16 +1429,17 @@ rt_status schedule(rt_server *srv)
             Request &r = srv->reqs[id];
             if (!ids.empty()) {
                 const Request &h = srv->reqs[ids[0]];
-                if (!compatible(h.seg, h.opts, r.seg, r.opts)) break;
+                if (!compatible(h.seg, h.opts, r.seg, r.opts)) continue;   // waits for its own launch
                 if (int(ids.size()) >= srv->max_batch_requests || rays + r.seg.n_rays > srv->max_batch_rays)
                     break;
             }
-            if (!srv->arena.alloc(r.bytes, r.off)) break;
+            if (!srv->arena.alloc(r.bytes, r.off)) break;             // memory admission stays FIFO
             ids.push_back(id);
             rays += r.seg.n_rays;
         }
         if (ids.empty()) return RT_OK;                        // wait for memory
-        srv->queue.erase(srv->queue.begin(), srv->queue.begin() + ptrdiff_t(ids.size()));
+        for (int64_t id : ids)
+            srv->queue.erase(std::find(srv->queue.begin(), srv->queue.end(), id));
         TraceJob job;
         for (int64_t id : ids) {
             Request &r = srv->reqs[id];
@@ -1710,7 +1805,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int32_t tail_threshold, waves_per_simd;
+    int32_t tail_threshold, waves_per_simd, ray_order;
 };
 
 std::mutex g_tune_mu;
@@ -1744,6 +1839,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
         if (it != g_tune_cache.end()) {
             tuned->tail_threshold = it->second.tail_threshold;
             tuned->waves_per_simd = it->second.waves_per_simd;
+            tuned->ray_order = it->second.ray_order;
             inf.from_cache = 1;
             if (info) *info = inf;
             return RT_OK;
@@ -1764,8 +1860,9 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     r.apogee_km = r.group_km + 4 * N; r.land_lat_deg = r.group_km + 5 * N; r.land_lon_deg = r.group_km + 6 * N;
     r.status = reinterpret_cast<int32_t *>(buf + 7 * N * 8);
     r.n_steps = r.status + N;
-    const int tails[4] = {-1, ctx->n_cu * 8, ctx->n_cu * 16, ctx->n_cu * 32};
+    const int tails[4] = {-2, -1, ctx->n_cu * 8, ctx->n_cu * 16};
     const int occs[2] = {1, 2};
+    const int orders[2] = {1, 2};
     auto time_opts = [&](rt_trace_opts o, double &ms) -> rt_status {
         o.results_mem = RT_MEM_DEVICE;
         ms = 1e300;
@@ -1777,20 +1874,24 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
         return RT_OK;
     };
     double best = 1e300;
-    TuneVal bv{0, 0};
+    TuneVal bv{0, 0, 0};
     rt_trace_opts o = *base;
     o.tail_threshold = 0;
     o.waves_per_simd = 0;
+    o.ray_order = 0;
     st = time_opts(o, inf.default_ms);
     for (int oc : occs) {
         for (int tl : tails) {
-            if (st != RT_OK) break;
-            o.tail_threshold = tl;
-            o.waves_per_simd = oc;
-            double ms = 0;
-            st = time_opts(o, ms);
-            ++inf.n_candidates;
-            if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc}; }
+            for (int od : orders) {
+                if (st != RT_OK) break;
+                o.tail_threshold = tl;
+                o.waves_per_simd = oc;
+                o.ray_order = od;
+                double ms = 0;
+                st = time_opts(o, ms);
+                ++inf.n_candidates;
+                if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od}; }
+            }
         }
     }
     (void)hipFree(buf);
@@ -1798,6 +1899,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     inf.best_ms = best;
     tuned->tail_threshold = bv.tail_threshold;
     tuned->waves_per_simd = bv.waves_per_simd;
+    tuned->ray_order = bv.ray_order;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = bv;
@@ -1812,12 +1914,13 @@ extern "C" rt_status rt_tune_cache_save(const char *path)
     std::ofstream f(path);
     if (!f) return RT_E_INVALID;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    f << "# n_cu n_lat n_lon n_h interp precision field log2_rays -> tail_threshold waves_per_simd\n";
+    f << "# n_cu n_lat n_lon n_h interp precision field log2_rays -> tail_threshold waves_per_simd "
+         "ray_order\n";
     for (const auto &kv : g_tune_cache) {
         const TuneKey &k = kv.first;
         f << k.n_cu << ' ' << k.n_lat << ' ' << k.n_lon << ' ' << k.n_h << ' ' << k.interp << ' '
           << k.precision << ' ' << k.field << ' ' << k.log2_rays << ' ' << kv.second.tail_threshold << ' '
-          << kv.second.waves_per_simd << '\n';
+          << kv.second.waves_per_simd << ' ' << kv.second.ray_order << '\n';
     }
     return f.good() ? RT_OK : RT_E_INVALID;
 }
@@ -1835,9 +1938,14 @@ extern "C" rt_status rt_tune_cache_load(const char *path)
         TuneKey k{};
         TuneVal v{};
         if (!(ss >> k.n_cu >> k.n_lat >> k.n_lon >> k.n_h >> k.interp >> k.precision >> k.field >>
-              k.log2_rays >> v.tail_threshold >> v.waves_per_simd))
+              k.log2_rays >> v.tail_threshold >> v.waves_per_simd >> v.ray_order))
             return RT_E_INVALID;
-        if (v.waves_per_simd < 0 || v.waves_per_simd > 2 || v.tail_threshold > (1 << 24)) return RT_E_INVALID;
+        std::string rest;
+        if (ss >> rest) return RT_E_INVALID;
+        if (v.waves_per_simd < 0 || v.waves_per_simd > 2 || v.tail_threshold > (1 << 24) ||
+            v.tail_threshold < -2 ||
+            v.ray_order < 0 || v.ray_order > 2)
+            return RT_E_INVALID;
         loaded[k] = v;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);

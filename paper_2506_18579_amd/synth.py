@@ -209,17 +209,38 @@ def sub_fan(fan: Fan, elev_idx=None, az_idx=None, freq_idx=None, modes=None) -> 
 
 
 def serving_requests(n_requests: int, seed: int = 1234, n_snapshots: int = 4,
-                     max_rays: int = 20000, qps: float = 50.0):
+                     max_rays: int = 20000, qps: float = 50.0, ionogram_fraction: float = 0.0):
     """Poisson request stream of ray fans of log-uniform size 1..max_rays.
 
     Each request: arrival time, snapshot id, fan (elevation start U[1, 60],
     width U[1, 30]; azimuth centre U[-180, 180], width U[0, 60]; one
     frequency U[3, 30] MHz; O, X or both with probability 1/3 each), laid
-    out as n_el x n_az with n_az = ceil(sqrt(N)/2)."""
+    out as n_el x n_az with n_az = ceil(sqrt(N)/2).
+
+    With ionogram_fraction > 0, that fraction of the requests (decided by a
+    second PCG64 stream, seed + 1, so the fan draws are unchanged) are
+    ionogram-synthesis requests instead: the 1200 km link of
+    ionogram_workload, 50 elevations (1..80 deg) x O/X x a run of 5..40
+    consecutive 0.1 MHz frequencies starting at U{2.0..26.0} MHz, with an
+    'ionogram' entry (receiver range, points per trace) and that
+    workload's exit height and maximum group path in 'opts'."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    rng_kind = np.random.Generator(np.random.PCG64(seed + 1))
+    (tlat, tlon), _ = link_endpoints()
     t = 0.0
     reqs = []
     for k in range(n_requests):
+        if ionogram_fraction > 0.0 and rng_kind.uniform() < ionogram_fraction:
+            t += rng.exponential(1.0 / qps)
+            snap = int(rng_kind.integers(0, n_snapshots))
+            n_f = int(rng_kind.integers(5, 41))
+            f0 = 2.0 + 0.1 * int(rng_kind.integers(0, 241))
+            freqs = np.round(f0 + 0.1 * np.arange(n_f), 10)
+            fan = Fan(tlat, tlon, 0.0, np.linspace(1.0, 80.0, 50), np.array([0.0]), freqs, (1, -1))
+            reqs.append(dict(id=k, t_arrive=t, snapshot=snap, fan=fan,
+                             ionogram=dict(range_km=1200.0, max_points=8),
+                             opts=dict(max_group_km=8000.0, exit_h_km=1000.0)))
+            continue
         t += rng.exponential(1.0 / qps)
         n = int(math.floor(math.exp(rng.uniform(0.0, math.log(max_rays)))))
         n = max(1, min(n, max_rays))

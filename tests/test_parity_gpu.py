@@ -232,20 +232,24 @@ def test_grid_create_rejects_bad_values(rt, ctx):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_tail_kernel_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
-    """The sixteen-lanes-per-ray tail kernel splits only the stencil
-    contraction and combines it in the one-lane order: outputs are
-    identical whether a ray finishes in the one-lane kernel (hand-off off),
-    runs entirely in the tail kernel (threshold above the ray count, so
-    every ray is handed off at the first check) or is handed off midway."""
+    """The sixteen-lanes-per-ray path splits only the stencil contraction
+    and combines it in the one-lane order: outputs are identical whether a
+    ray finishes in the one-lane kernel (hand-off off), runs entirely in the
+    tail kernel (threshold above the ray count, so every ray is handed off
+    at the first check), is handed off midway, or finishes on a 16-lane row
+    of its own wave (in-wave switch), in either visiting order."""
     fan = _subfan(aniso_wl)
     one = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=-1)
     tail = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision,
                      tail_threshold=1 << 20)
     mid = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=100)
+    inwave = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=-2)
+    strided = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, precision=precision, tail_threshold=-2,
+                        ray_order=2)
     for k in ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "status", "n_steps"):
-        assert np.array_equal(one[k], tail[k], equal_nan=True), k
-        assert np.array_equal(one[k], mid[k], equal_nan=True), k
-    assert one["total_steps"] == tail["total_steps"] == mid["total_steps"]
+        for other in (tail, mid, inwave, strided):
+            assert np.array_equal(one[k], other[k], equal_nan=True), k
+    assert one["total_steps"] == tail["total_steps"] == mid["total_steps"] == inwave["total_steps"]
 
 
 def test_single_ray_is_handed_off(rt, ctx, aniso_wl, aniso_grid):

@@ -147,3 +147,25 @@ def test_cancel_and_errors(rt, ctx, grids):
         assert srv.fetch(z, 0)["status"].size == 0
     finally:
         srv.close()
+
+
+def test_ionogram_requests_in_the_mix(rt, ctx, grids):
+    """Ionogram-synthesis requests among fan requests: each sweep and its
+    extracted traces equal those computed alone."""
+    from paper_2506_18579_amd import serve
+    reqs = synth.serving_requests(16, seed=11, n_snapshots=len(grids), max_rays=2000, qps=1e9,
+                                  ionogram_fraction=0.4)
+    assert sum("ionogram" in r for r in reqs) >= 3
+    srv = rt.Server(ctx, n_slots=4, mem_budget_bytes=64 << 20)
+    try:
+        out = serve.replay(srv, grids, reqs, opts("mixed"), keep_results=True)
+    finally:
+        srv.close()
+    for k, r in enumerate(reqs):
+        o = dict(opts("mixed"), **r.get("opts", {}))
+        alone = rt.trace(ctx, grids[r["snapshot"]], r["fan"], **o)
+        same(out["results"][k], alone)
+        if "ionogram" in r:
+            pts, cnt = rt.ionogram(ctx, r["fan"], alone, 1200.0, 8)
+            mp, mc = out["results"][k]["ionogram"]
+            assert np.array_equal(cnt, mc) and np.array_equal(pts, mp, equal_nan=True)

@@ -52,13 +52,14 @@ def test_autotune_choice_is_cached_and_result_neutral(rt, ctx, grid, wl, tmp_pat
     kw = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km)
     rt.tune_cache_clear()
     t = rt.autotune(ctx, grid, fan, precision="mixed", **kw)
-    assert not t["from_cache"] and t["n_candidates"] == 8
+    assert not t["from_cache"] and t["n_candidates"] == 16
     assert t["waves_per_simd"] in (1, 2)
-    assert t["tail_threshold"] == -1 or t["tail_threshold"] % 8 == 0
+    assert t["tail_threshold"] in (-2, -1) or t["tail_threshold"] % 8 == 0
+    assert t["ray_order"] in (1, 2)
     assert 0 < t["best_ms"] <= 1.5 * t["default_ms"]
     t2 = rt.autotune(ctx, grid, fan, precision="mixed", **kw)
-    assert t2["from_cache"] and (t2["tail_threshold"], t2["waves_per_simd"]) == \
-        (t["tail_threshold"], t["waves_per_simd"])
+    assert t2["from_cache"] and (t2["tail_threshold"], t2["waves_per_simd"], t2["ray_order"]) == \
+        (t["tail_threshold"], t["waves_per_simd"], t["ray_order"])
     p = tmp_path / "tune.txt"
     rt.tune_cache_save(str(p))
     rt.tune_cache_clear()
@@ -66,7 +67,7 @@ def test_autotune_choice_is_cached_and_result_neutral(rt, ctx, grid, wl, tmp_pat
     assert rt.autotune(ctx, grid, fan, precision="mixed", **kw)["from_cache"]
     a = rt.trace(ctx, grid, fan, precision="mixed", **kw)
     b = rt.trace(ctx, grid, fan, precision="mixed", tail_threshold=t["tail_threshold"],
-                 waves_per_simd=t["waves_per_simd"], **kw)
+                 waves_per_simd=t["waves_per_simd"], ray_order=t["ray_order"], **kw)
     for k in KEYS:
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
