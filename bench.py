@@ -38,10 +38,10 @@ PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB device copy
 # in the same runs).  Valid only for the kernel sources with these hashes;
 # otherwise the traffic is reported as null.
-TRAFFIC_BYTES = (32288 + 23643) * 1024
+TRAFFIC_BYTES = (38608 + 23417) * 1024
 TRAFFIC_SOURCES = {
-    "rtgd.hip": "7795b99e7612e01719bbf30a915ea0646a2de9796de24be4a0cc885dda6afe22",
-    "rtgd_device.h": "f5917413459a0d487d9f757027151259853bf3cc605d55d5b77f80fa142033a0",
+    "rtgd.hip": "42096eef44c271e58ae843d03de2210152364c08a0c33302d7b6faf93c846844",
+    "rtgd_device.h": "49134116459e193daf927991639888a76e834160c6241765ef56355dcebc0f76",
 }
 
 
