@@ -109,6 +109,15 @@ def main():
     tune32 = rtgd.autotune(ctx, grid, wl.fan, precision="mixed", **wkw)
     fp64 = time_trace(rtgd, torch, ctx, grid, wl, "fp64", a.steps, a.warmup, tune64)
     mixed = time_trace(rtgd, torch, ctx, grid, wl, "mixed", max(1, a.steps), 1, tune32)
+    # end to end: per-ray results copied back to host memory inside each call
+    e2e = []
+    for _ in range(3):
+        t = time.perf_counter()
+        r = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
+                       exit_h_km=wl.exit_km, precision="fp64", tail_threshold=tune64["tail_threshold"],
+                       waves_per_simd=tune64["waves_per_simd"], ray_order=tune64["ray_order"])
+        e2e.append((time.perf_counter() - t, r["total_steps"]))
+    e2e_ms = float(np.median([x[0] for x in e2e])) * 1e3
     fan_wl = synth.aniso_fan_workload(0)
     fan_grid = rtgd.Grid(ctx, fan_wl.grid)
     fan64 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "fp64", max(3, a.steps), 1)
@@ -162,6 +171,7 @@ def main():
     res32 = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in mixed["out"].items()}
 
     cpu = None
+    cpu_1thread = None
     accuracy = {}
     if not a.no_cpu:
         from oracle import oracle as O
@@ -181,6 +191,17 @@ def main():
                "sample": f"every {a.cpu_sample_stride}. ray of the 112,400-ray ionogram sweep "
                          f"({idx.size} rays, {o['total_steps']} ray-steps, {dt:.1f} s, "
                          f"plain FP64 C, OpenMP over rays)"}
+        # one host thread on a bounded sample (every 64th ray)
+        idx1 = np.arange(0, wl.fan.n_rays, 64)
+        t = time.perf_counter()
+        o1 = O.trace(med, e[idx1], az[idx1], f[idx1], m[idx1], B0=wl.grid.B0_T,
+                     R=wl.grid.geom.earth_radius_km,
+                     tx=(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km),
+                     step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km, nthreads=1)
+        dt1 = time.perf_counter() - t
+        cpu_1thread = {"value": o1["total_steps"] / dt1, "unit": "ray-steps/s", "cores": 1,
+                       "sample": f"every 64th ray ({idx1.size} rays, {o1['total_steps']} ray-steps, "
+                                 f"{dt1:.1f} s)"}
         same = (res64["status"][idx] == o["status"])
         scale = lambda k, fl: np.abs(res64[k][idx][same] - o[k][same]) / np.maximum(np.abs(o[k][same]), fl)
         relv = np.max([scale(k, 1.0) for k in ("group_km", "phase_km", "range_km", "az_dev_deg")], axis=0)
@@ -257,6 +278,11 @@ def main():
                      "kernel_ms_avg": kms, "flops_per_ray_step": FLOPS_PER_STEP_ANISO},
         "tuning": {"fp64": tune64, "mixed": tune32},
         "cpu_baseline": cpu,
+        "cpu_oracle_1thread": cpu_1thread,
+        "end_to_end_host_results": {"ms_per_sweep": e2e_ms,
+                                    "ray_steps_per_s": e2e[-1][1] / (e2e_ms * 1e-3),
+                                    "note": "fan upload, both kernels and the 8 MB result copy "
+                                            "to pageable host memory"},
         "accuracy": accuracy,
         "mixed": {"value": mixed["ray_steps"] / mixed["elapsed"],
                   "kernel_ms_avg": float(np.mean(mixed["kernel_ms"])),
