@@ -182,6 +182,16 @@ __device__ __forceinline__ void sincos_add(double s0, double c0, double d, doubl
     s = fm(s0, cd, c0 * sd);
     c = fm(c0, cd, -(s0 * sd));
 }
+// The same for |d| <= 2^-10, with the series cut after the d^5 (sine) and
+// d^6 (cosine) terms: the first omitted terms are below 2e-25 and 3e-29.
+__device__ __forceinline__ void sincos_add_small(double s0, double c0, double d, double &s, double &c)
+{
+    double d2 = d * d;
+    double sd = d * fm(-d2 * (1.0 / 6.0), fm(-d2, 1.0 / 20.0, 1.0), 1.0);
+    double cd = fm(-d2 * 0.5, fm(-d2 * (1.0 / 12.0), fm(-d2, 1.0 / 30.0, 1.0), 1.0), 1.0);
+    s = fm(s0, cd, c0 * sd);
+    c = fm(c0, cd, -(s0 * sd));
+}
 
 // Cross-lane exchange through DPP (no LDS round trip), on the two 32-bit
 // halves of a double: quad permutations within groups of 4 lanes and the
@@ -311,11 +321,10 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
     T uref = T(0);
     if constexpr (sizeof(T) == 4) uref = (LANES == 1) ? sc.u[1][1][1] : sc.uref;
 
-    T wh[4], dwh[4];
-    weights4<T, IP>(T(sh_), wh, dwh);
-
     T v, glat, glon, gh;
     if constexpr (LANES == 1) {
+        T wh[4], dwh[4];
+        weights4<T, IP>(T(sh_), wh, dwh);
         T wo[4], dwo[4], wl[4], dwl[4];
         weights4<T, IP>(T(so_), wo, dwo);
         weights4<T, IP>(T(sl_), wl, dwl);
@@ -347,9 +356,17 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
         glon = (plo[0] + plo[3]) + (plo[1] + plo[2]);
         gh = (phh[0] + phh[3]) + (phh[1] + phh[2]);
     } else {
-        T wo, dwo, wl, dwl;
+        T wo, dwo, wl, dwl, w1, dw1;
         eval_piece<T, IP>(sc.pb, T(so_), wo, dwo);
         eval_piece<T, IP>(sc.pa, T(sl_), wl, dwl);
+        // height weights: lane b of each quad evaluates node b's piece (the
+        // same piece as its longitude weight), the quad shares them
+        eval_piece<T, IP>(sc.pb, T(sh_), w1, dw1);
+        T wh[4], dwh[4];
+        wh[0] = dpp<0x00>(w1); dwh[0] = dpp<0x00>(dw1);
+        wh[1] = dpp<0x55>(w1); dwh[1] = dpp<0x55>(dw1);
+        wh[2] = dpp<0xAA>(w1); dwh[2] = dpp<0xAA>(dw1);
+        wh[3] = dpp<0xFF>(w1); dwh[3] = dpp<0xFF>(dw1);
         T uu[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) uu[c] = sc.u[0][0][c] - uref;
@@ -526,7 +543,9 @@ __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc
         double st = s0, ct = c0;
         const double d = t[1] - y[1];
         if (stage > 0) {
-            if (fabs(d) <= 0.05) sincos_add(s0, c0, d, st, ct);
+            const double ad = fabs(d);
+            if (ad <= 0x1p-10) sincos_add_small(s0, c0, d, st, ct);
+            else if (ad <= 0.05) sincos_add(s0, c0, d, st, ct);
             else sincos(t[1], &st, &ct);
         }
         ok &= ray_rhs<T, IP, LANES>(g, rc, t, T(st), T(ct), sc, k);
