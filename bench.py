@@ -36,12 +36,12 @@ PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 
 # HBM bytes of one FP64 ionogram launch (k_trace + k_tail) from rocprofv3:
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB device copy
-# in the same runs).  Valid only for the kernel sources with these hashes;
-# otherwise the traffic is reported as null.
-TRAFFIC_BYTES = (38608 + 23417) * 1024
+# in the same runs).  Valid only for the device sources (per-step arithmetic
+# and trace kernels) with these hashes; otherwise reported as null.
+TRAFFIC_BYTES = (38646 + 23478) * 1024
 TRAFFIC_SOURCES = {
-    "rtgd.hip": "42096eef44c271e58ae843d03de2210152364c08a0c33302d7b6faf93c846844",
-    "rtgd_device.h": "49134116459e193daf927991639888a76e834160c6241765ef56355dcebc0f76",
+    "rtgd_device.h": "e0567561595ae14abf0a5581df28a5f9300abfeaf5f553c71285b4d5b575fb24",
+    "rtgd_kernels.h": "a7ca94f2b242d5d80b9cd2056156fb759c94ee2006426a0cc0d341e50b744969",
 }
 
 

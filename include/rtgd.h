@@ -299,10 +299,12 @@ void rt_plan_destroy(rt_plan *plan);
 /* ------------------------------------------------------------------------
  * Autotuner.  The launch settings that change speed but not results are
  * tail_threshold, waves_per_simd and ray_order (see rt_trace_opts).
- * rt_autotune traces the given fan once per candidate setting
+ * rt_autotune traces the given fan for every candidate setting
  * (tail_threshold in {-2, -1, 8 and 16 rays per CU} x waves_per_simd
- * in {1, 2} x ray_order in {index, strided}), keeps the fastest by device
- * time and writes base with those three fields replaced to *tuned.  Choices are cached in the process under a key made of the
+ * in {1, 2} x ray_order in {index, strided}; one untimed run, then the
+ * median device time of three), keeps the fastest if it beats the library
+ * defaults by at least 2 % (else the defaults, all three fields 0) and
+ * writes base with those three fields replaced to *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on
  * or off and the ray count rounded to a power of two; a cached key is
  * answered without tracing.  Results of the trial traces are discarded

@@ -1,16 +1,6 @@
-// rtgd.hip -- librtgd: persistent ray-tracing kernel for gfx950 and the
-// C-ABI host side (contexts, grids, fields, traces).
-//
-// Design (one MI355X):
-//   * one lane integrates one ray; its state (position, wave normal, phase
-//     and group path) lives in registers for the ray's whole life;
-//   * a persistent grid of single-wave workgroups pulls rays from a device
-//     queue: when a lane's ray terminates the wave refills every idle lane
-//     with one atomic (ballot + popcount), so waves stay full while rays of
-//     very different lengths retire at different times;
-//   * the density grid stays resident in HBM and is re-read through the L2
-//     and Infinity Cache; nothing on the path is a dense contraction, so
-//     all arithmetic is VALU (no MFMA).
+// rtgd.hip -- librtgd: the C-ABI host side (contexts, grids, fields,
+// traces, ionograms, the request server, graph plans, the autotuner) around
+// the trace kernels of rtgd_kernels.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,544 +21,7 @@
 
 #include "rtgd.h"
 #include "rtgd_device.h"
-
-using namespace rtgd;
-
-namespace {
-
-// ---------------------------------------------------------------------------
-// Kernel parameters (one block in device memory per launch)
-// ---------------------------------------------------------------------------
-
-// One request of a launch: launch rays [start, start + n) are its fan, in
-// the order ((i_f * n_mode + i_m) * n_elev + i_e) * n_az + i_a.  A launch
-// holds one segment (rt_trace) or a batch of requests (the server) that
-// share the grid geometry, the transmitter and the step options.
-struct Segment {
-    const double *elev, *az, *freq;  // device copies of the fan axes
-    const void *v;                   // grid values (T) of the request's grid
-    double B0;                       // 0: isotropic
-    double *out[7];                  // group, phase, range, az_dev, apogee, land_lat, land_lon
-    int32_t *status, *nsteps;
-    unsigned long long *steps;       // RK4 steps of the request (accumulated)
-    int32_t n_elev, n_az, n_mode;
-    int32_t mode_first;              // +1 if the first mode is O, -1 if X
-    int32_t start, n;
-};
-
-template <typename T>
-struct TraceParams {
-    GridDev<T> g;
-    const Segment *seg;
-    int32_t n_seg;
-    int32_t n_rays;            // over all segments
-    double tx_lon;             // rad
-    double up[3], north[3], east[3];   // transmitter frame (Cartesian)
-    double r0;                 // R + tx height
-    double step, max_group, exit_h, floor_h;
-    int32_t max_steps;         // hard cap (never reached before max_group)
-    int32_t traj_stride;
-    int64_t traj_per_ray;
-    double *traj;              // trajectories, indexed by launch ray (one segment only)
-    int32_t *traj_count;
-    // scheduling
-    int32_t *queue_head;
-    int32_t *truncated;
-    // hand-off of the last live rays to the 4-lanes-per-ray tail kernel
-    int32_t *live;             // rays neither finished nor handed off
-    int32_t *n_handoff;        // records written
-    struct Handoff *handoff;   // capacity handoff_threshold
-    int32_t handoff_threshold; // hand off once at most this many rays are live (0: never);
-                               // also the hand-off buffer capacity
-    int32_t inwave;            // a drained wave with <= 4 live rays finishes them 16 lanes each
-    int64_t perm_stride;       // launch ray q is visited as (q * perm_stride) mod n_rays
-};
-
-// State of a ray moved from the one-lane to the sixteen-lane kernel.
-struct Handoff {
-    double y[7];
-    double gp, apogee;
-    int32_t ray, steps, ntraj, pad;
-};
-
-__device__ __forceinline__ double dot3(const double a[3], const double b[3])
-{
-    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
-
-// longitude of (x, y) unwrapped to within pi of ref
-__device__ __forceinline__ double lon_near(double x, double y, double ref)
-{
-    double p = atan2(y, x);
-    return p + 2.0 * kPi * floor((ref - p) / (2.0 * kPi) + 0.5);
-}
-
-__device__ __forceinline__ void sph_basis(double th, double ph, double rh[3], double thh[3],
-                                          double phh[3])
-{
-    double st, ct, sp, cp;
-    sincos(th, &st, &ct);
-    sincos(ph, &sp, &cp);
-    rh[0] = st * cp; rh[1] = st * sp; rh[2] = ct;
-    thh[0] = ct * cp; thh[1] = ct * sp; thh[2] = -st;
-    phh[0] = -sp; phh[1] = cp; phh[2] = 0.0;
-}
-
-__device__ __forceinline__ void cart_to_state(const double x[3], const double d[3], double ref_lon,
-                                              double y[7])
-{
-    double r = sqrt(dot3(x, x));
-    double th = atan2(sqrt(x[0] * x[0] + x[1] * x[1]), x[2]);
-    double ph = lon_near(x[0], x[1], ref_lon);
-    double rh[3], thh[3], phh[3];
-    sph_basis(th, ph, rh, thh, phh);
-    y[0] = r; y[1] = th; y[2] = ph;
-    y[3] = dot3(d, rh);
-    y[4] = dot3(d, thh);
-    y[5] = dot3(d, phh);
-}
-
-__device__ __forceinline__ void state_to_cart(const double y[7], double x[3], double d[3])
-{
-    double rh[3], thh[3], phh[3];
-    sph_basis(y[1], y[2], rh, thh, phh);
-    double inv = 1.0 / sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        x[i] = y[0] * rh[i];
-        d[i] = (y[3] * rh[i] + y[4] * thh[i] + y[5] * phh[i]) * inv;
-    }
-}
-
-// Per-lane ray bookkeeping.
-struct Lane {
-    double y[7];          // r, th, ph, n_r, n_th, n_ph, P
-    double gp;            // group path P'
-    double apogee;
-    double az0;           // launch azimuth (deg)
-    RayConst rc;
-    int32_t steps;
-    int32_t ntraj;
-    int32_t seg;          // segment of the ray
-    int32_t local;        // ray index within the segment
-};
-
-template <typename T>
-__device__ __forceinline__ void put_traj(const TraceParams<T> &P, int ray, Lane &L)
-{
-    if (L.ntraj < P.traj_per_ray) {
-        double *rec = P.traj + (size_t(ray) * size_t(P.traj_per_ray) + size_t(L.ntraj)) * 8;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) rec[i] = L.y[i];
-        rec[6] = L.gp;
-        rec[7] = L.y[6];
-        ++L.ntraj;
-    } else {
-        *P.truncated = 1;
-    }
-}
-
-// Per-ray constants from the launch ray index: find the segment (binary
-// search over the segment starts), then decode its fan.
-template <typename T>
-__device__ __forceinline__ void ray_const(const TraceParams<T> &P, int ray, Lane &L, double &elev)
-{
-    int lo = 0, hi = P.n_seg - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (P.seg[mid].start <= ray) lo = mid;
-        else hi = mid - 1;
-    }
-    const Segment &S = P.seg[lo];
-    int i = ray - S.start;
-    L.seg = lo;
-    L.local = i;
-    int ia = i % S.n_az; i /= S.n_az;
-    int ie = i % S.n_elev; i /= S.n_elev;
-    int im = i % S.n_mode; i /= S.n_mode;
-    int jf = i;
-    elev = S.elev[ie];
-    double f = S.freq[jf];
-    int sigma = (im == 0) ? S.mode_first : -1;
-    L.rc.v = S.v;
-    L.rc.inv_f2 = 1.0 / (f * f);
-    L.rc.Y0 = kKB * S.B0 / (f * 1e6);
-    L.rc.sigma = (S.B0 == 0.0) ? 0 : sigma;
-    L.az0 = S.az[ia];
-}
-
-// Ray initialisation (Sec. II-C): straight vacuum line from the transmitter
-// to the grid bottom, |n| = 1 there.
-template <typename T>
-__device__ __forceinline__ void init_ray(const TraceParams<T> &P, int ray, Lane &L, bool write)
-{
-    double elev_deg;
-    ray_const(P, ray, L, elev_deg);
-    double sb, cb, sa, ca;
-    sincos(elev_deg * kDeg2Rad, &sb, &cb);
-    sincos(L.az0 * kDeg2Rad, &sa, &ca);
-    double d[3], x[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) d[k] = sb * P.up[k] + cb * (ca * P.north[k] + sa * P.east[k]);
-    double rb = P.g.R + P.floor_h;
-    double p = P.r0 * sb;
-    double c = rb * rb - P.r0 * P.r0;
-    double s = c / (p + sqrt(p * p + c));
-#pragma unroll
-    for (int k = 0; k < 3; ++k) x[k] = P.r0 * P.up[k] + s * d[k];
-    cart_to_state(x, d, P.tx_lon, L.y);
-    L.y[6] = s;
-    L.gp = s;
-    L.apogee = L.y[0] - P.g.R;
-    L.steps = 0;
-    L.ntraj = 0;
-    if (P.traj_stride > 0 && write) put_traj(P, ray, L);
-}
-
-// Outputs of a terminated ray: landing (or sub-ray) point, ground range,
-// azimuth deviation (Sec. II-C outputs, plus the phase path).
-template <typename T>
-__device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray, Lane &L, int status)
-{
-    double st, ct, sp, cp;
-    sincos(L.y[1], &st, &ct);
-    sincos(L.y[2], &sp, &cp);
-    double uL[3] = {st * cp, st * sp, ct};
-    const double *uT = P.up;
-    double cr[3] = {uT[1] * uL[2] - uT[2] * uL[1], uT[2] * uL[0] - uT[0] * uL[2],
-                    uT[0] * uL[1] - uT[1] * uL[0]};
-    double gam = atan2(sqrt(dot3(cr, cr)), dot3(uT, uL));
-    double azd = 0.0;
-    if (gam >= 1e-9) {
-        double bear = atan2(dot3(uL, P.east), dot3(uL, P.north)) * kRad2Deg;
-        double x = bear - L.az0;
-        azd = x - 360.0 * ceil((x - 180.0) / 360.0);
-    }
-    double o[7] = {L.gp, L.y[6], P.g.R * gam, azd, L.apogee, 90.0 - L.y[1] * kRad2Deg,
-                   L.y[2] * kRad2Deg};
-    if (status == kNumeric) {
-#pragma unroll
-        for (int k = 0; k < 7; ++k) o[k] = __builtin_nan("");
-    }
-    const Segment &S = P.seg[L.seg];
-    const int i = L.local;
-#pragma unroll
-    for (int k = 0; k < 7; ++k)
-        if (S.out[k]) S.out[k][i] = o[k];
-    if (S.status) S.status[i] = status;
-    if (S.nsteps) S.nsteps[i] = L.steps;
-    atomicAdd(S.steps, (unsigned long long)L.steps);
-    if (P.traj_count) P.traj_count[ray] = L.ntraj;
-}
-
-// One RK4 step plus the termination tests.  Returns the ray status, or -1
-// if the ray goes on.  `write` is false on the lanes of a row that only
-// shadow the row's leader (no memory writes).
-template <typename T, int IP, int LANES>
-__device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L, bool write,
-                                       StencilCache<T, LANES> &sc)
-{
-    bool ok = rk4_step<T, IP, LANES>(P.g, L.rc, L.y, P.step, sc);
-    L.gp += P.step;
-    ++L.steps;
-    double h = L.y[0] - P.g.R;
-    int status = -1;
-    int graze = 0;
-    double x[3], d[3], s = 0.0;
-    bool finite = ok;
-#pragma unroll
-    for (int i = 0; i < 7; ++i) finite = finite && isfinite(L.y[i]);
-    if (!finite) {
-        status = kNumeric;
-    } else if (h < P.floor_h && L.y[3] < 0.0) {
-        // below the grid bottom and descending: vacuum line to r = R
-        state_to_cart(L.y, x, d);
-        double xd = dot3(x, d);
-        double c = dot3(x, x) - P.g.R * P.g.R;
-        double disc = xd * xd - c;
-        if (disc >= 0.0) {
-            s = c / (-xd + sqrt(disc));
-            status = kGround;
-        } else {
-            // grazing line missing the Earth: back up to the grid bottom
-            double rb = P.g.R + P.floor_h;
-            double c2 = dot3(x, x) - rb * rb;
-            s = -xd + sqrt(xd * xd - c2);
-            graze = 1;
-        }
-    } else if (h >= P.exit_h) {
-        status = kEscape;
-    } else if (L.gp >= P.max_group || L.steps >= P.max_steps) {
-        status = kMaxPath;
-    }
-    if (status != kNumeric && h > L.apogee) L.apogee = h;
-    if (P.traj_stride > 0 && write && (L.steps % P.traj_stride == 0 || status >= 0)) put_traj(P, ray, L);
-
-    if (status == kGround) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) x[i] += s * d[i];
-        L.gp += s;
-        L.y[6] += s;
-        L.y[0] = sqrt(dot3(x, x));
-        L.y[1] = atan2(sqrt(x[0] * x[0] + x[1] * x[1]), x[2]);
-        L.y[2] = lon_near(x[0], x[1], P.tx_lon);
-    } else if (graze) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) x[i] += s * d[i];
-        L.gp += s;
-        double ph = L.y[6] + s;
-        cart_to_state(x, d, P.tx_lon, L.y);
-        L.y[6] = ph;
-    }
-    return status;
-}
-
-// wave-aggregated atomic add (lanes with pred), returns each lane's slot
-__device__ __forceinline__ int wave_append(int32_t *counter, bool pred, int lane)
-{
-    unsigned long long mask = __ballot(pred);
-    int base = 0;
-    if (mask) {
-        int leader = __ffsll((long long)mask) - 1;
-        if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-        base = __shfl(base, leader);
-    }
-    return base + __popcll(mask & ((1ull << lane) - 1ull));
-}
-
-// Sixteen lanes (a DPP row) per ray until every ray of the wave has
-// terminated; rows with ray < 0 idle.  The row's lanes hold identical state
-// and run identical arithmetic; only the stencil contraction is split (one
-// column per lane, see medium<T, IP, 16>), so the results equal the
-// one-lane kernel's bit for bit.  Lane 0 of the row writes.
-template <typename T, int IP>
-__device__ __forceinline__ void run_rows(const TraceParams<T> &P, int ray, Lane &L)
-{
-    const int lane = int(__lane_id());
-    const bool lead = (lane & 15) == 0;
-    StencilCache<T, 16> sc;
-    sc.clear();
-    sc.pa = piece<T, IP>((lane >> 2) & 3);
-    sc.pb = piece<T, IP>(lane & 3);
-    for (;;) {
-        if (__ballot(ray >= 0) == 0ull) break;
-        if (ray >= 0) {
-            int st = advance<T, IP, 16>(P, ray, L, lead, sc);
-            if (st >= 0) {
-                if (lead) finish_ray(P, ray, L, st);
-                ray = -1;
-            }
-        }
-    }
-}
-
-// Move the (at most four) live rays of the wave, marked in `live`, onto
-// the wave's four 16-lane rows, in lane order; rows without a ray get -1.
-__device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, Lane &L)
-{
-    const int row = int(__lane_id()) >> 4;
-    int src = -1;
-    unsigned long long m = live;
-    for (int i = 0; i < 4 && m; ++i) {
-        const int b = __ffsll((long long)m) - 1;
-        if (i == row) src = b;
-        m &= m - 1ull;
-    }
-    const int s = src < 0 ? 0 : src;
-    Lane M;
-#pragma unroll
-    for (int i = 0; i < 7; ++i) M.y[i] = __shfl(L.y[i], s);
-    M.gp = __shfl(L.gp, s);
-    M.apogee = __shfl(L.apogee, s);
-    M.az0 = __shfl(L.az0, s);
-    M.rc.v = reinterpret_cast<const void *>(
-        __shfl((unsigned long long)reinterpret_cast<uintptr_t>(L.rc.v), s));
-    M.rc.inv_f2 = __shfl(L.rc.inv_f2, s);
-    M.rc.Y0 = __shfl(L.rc.Y0, s);
-    M.rc.sigma = __shfl(L.rc.sigma, s);
-    M.steps = __shfl(L.steps, s);
-    M.ntraj = __shfl(L.ntraj, s);
-    M.seg = __shfl(L.seg, s);
-    M.local = __shfl(L.local, s);
-    const int r = __shfl(ray, s);
-    L = M;
-    ray = src < 0 ? -1 : r;
-}
-
-// Persistent one-lane-per-ray kernel.  Each 64-lane wave loops { refill
-// idle lanes from the queue; one RK4 step on every live lane } until the
-// queue is drained and every lane is idle.  Rays are visited in the order
-// (q * perm_stride) mod n_rays, which spreads runs of neighbouring (and
-// similarly long) rays over many waves.  Once the queue is drained, either
-//   * (inwave) a wave left with at most four live rays moves them onto its
-//     four 16-lane rows and finishes them there, or
-//   * (handoff_threshold > 0) once at most handoff_threshold rays are live
-//     in the whole launch, each remaining ray's state is written to the
-//     hand-off buffer and the lane retires (the tail kernel finishes it with
-//     sixteen lanes per ray).
-// Every ray terminates (the group path grows by one step per iteration up
-// to max_group), so every wave exits.
-template <typename T, int IP>
-__device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp)
-{
-    const TraceParams<T> &P = *Pp;
-    const int lane = int(__lane_id());
-    int ray = -1;            // -1 idle, -2 queue drained, >= 0 live ray
-    bool drained = false;
-    unsigned long long to_rows = 0ull;   // live rays moving to 16-lane rows
-    Lane L;
-    StencilCache<T, 1> sc;
-    sc.clear();
-    for (int iter = 0;; ++iter) {
-        bool need = (ray == -1);
-        if (__ballot(need)) {
-            int q = wave_append(P.queue_head, need, lane);
-            if (need) {
-                if (q < P.n_rays) {
-                    ray = int((unsigned long long)q * (unsigned long long)P.perm_stride %
-                              (unsigned long long)P.n_rays);
-                    init_ray(P, ray, L, true);
-                } else {
-                    ray = -2;
-                }
-            }
-            drained = drained || __ballot(ray == -2) != 0ull;
-        }
-        const unsigned long long livem = __ballot(ray >= 0);
-        if (livem == 0ull) break;
-        if (P.inwave && drained && __popcll(livem) <= 4) {
-            to_rows = livem;
-            break;
-        }
-        if (P.handoff_threshold > 0 && (iter & 7) == 0) {
-            int live = 0, head = 0;
-            if (lane == 0) {
-                live = __hip_atomic_load(P.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                head = __hip_atomic_load(P.queue_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            live = __shfl(live, 0);
-            head = __shfl(head, 0);
-            if (head >= P.n_rays && live <= P.handoff_threshold) {
-                bool hand = ray >= 0;
-                int slot = wave_append(P.n_handoff, hand, lane);
-                if (hand) {
-                    Handoff &H = P.handoff[slot];
-#pragma unroll
-                    for (int i = 0; i < 7; ++i) H.y[i] = L.y[i];
-                    H.gp = L.gp;
-                    H.apogee = L.apogee;
-                    H.ray = ray;
-                    H.steps = L.steps;
-                    H.ntraj = L.ntraj;
-                    H.pad = 0;
-                    ray = -2;
-                }
-                unsigned long long hm = __ballot(hand);
-                if (lane == 0 && hm) atomicSub(P.live, __popcll(hm));
-                break;
-            }
-        }
-        int st = -1;
-        if (ray >= 0) {
-            st = advance<T, IP, 1>(P, ray, L, true, sc);
-            if (st >= 0) {
-                finish_ray(P, ray, L, st);
-                ray = -1;
-            }
-        }
-        unsigned long long fin = __ballot(st >= 0);
-        if (lane == 0 && fin && P.handoff_threshold > 0) atomicSub(P.live, __popcll(fin));
-    }
-    // after the one-lane loop, so that its stencil cache is dead here
-    if (to_rows) {
-        gather_rows(to_rows, ray, L);
-        run_rows<T, IP>(P, ray, L);
-    }
-}
-
-// Tail kernel: sixteen lanes (a DPP row) per handed-off ray, four rays per
-// wave.  The row's lanes hold identical state and run identical arithmetic;
-// only the stencil contraction is split (one column per lane, see
-// medium<T, IP, 16>), so the results equal the one-lane kernel's bit for
-// bit.  Lane 0 of the row writes.  Launched with enough rows for the
-// hand-off capacity; rows past the number of records exit at once.
-template <typename T, int IP>
-__device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
-{
-    const TraceParams<T> &P = *Pp;
-    const int lane = int(__lane_id());
-    const int slot = int(blockIdx.x) * 4 + (lane >> 4);
-    const int n = *P.n_handoff;
-    int ray = -1;
-    Lane L;
-    if (slot < n) {
-        const Handoff &H = P.handoff[slot];
-        ray = H.ray;
-        double elev_unused;
-        ray_const(P, ray, L, elev_unused);
-#pragma unroll
-        for (int i = 0; i < 7; ++i) L.y[i] = H.y[i];
-        L.gp = H.gp;
-        L.apogee = H.apogee;
-        L.steps = H.steps;
-        L.ntraj = H.ntraj;
-    }
-    run_rows<T, IP>(P, ray, L);
-}
-
-// Oblique-ionogram extraction: one thread per (frequency, mode) trace scans
-// its elevations for ground-range crossings of the receiver distance.
-__global__ __launch_bounds__(64) void k_ionogram(const double *__restrict__ elev, int n_elev,
-                                                 int n_trace, const double *__restrict__ group,
-                                                 const double *__restrict__ phase,
-                                                 const double *__restrict__ range,
-                                                 const double *__restrict__ apogee,
-                                                 const int32_t *__restrict__ status, double D,
-                                                 int max_points, double *__restrict__ out,
-                                                 int32_t *__restrict__ counts)
-{
-    int t = int(blockIdx.x) * 64 + int(threadIdx.x);
-    if (t >= n_trace) return;
-    int found = 0;
-    const size_t base = size_t(t) * size_t(n_elev);
-    for (int e = 0; e + 1 < n_elev; ++e) {
-        size_t i0 = base + e, i1 = i0 + 1;
-        if (status[i0] != kGround || status[i1] != kGround) continue;
-        double d0 = range[i0] - D, d1 = range[i1] - D;
-        if ((d0 < 0.0) == (d1 < 0.0)) continue;
-        if (found < max_points) {
-            double w = d0 / (d0 - d1);
-            double *o = out + (size_t(t) * size_t(max_points) + size_t(found)) * 4;
-            o[0] = fm(w, elev[e + 1] - elev[e], elev[e]);
-            o[1] = fm(w, group[i1] - group[i0], group[i0]);
-            o[2] = fm(w, phase[i1] - phase[i0], phase[i0]);
-            o[3] = fm(w, apogee[i1] - apogee[i0], apogee[i0]);
-        }
-        ++found;
-    }
-    // unused slots are defined (zero), never stale memory
-    for (int k = found; k < max_points; ++k) {
-        double *o = out + (size_t(t) * size_t(max_points) + size_t(k)) * 4;
-        o[0] = o[1] = o[2] = o[3] = 0.0;
-    }
-    counts[t] = found;
-}
-
-// Launch wrappers.  The *_w2 variants ask the compiler to fit two waves per
-// SIMD (at most 256 VGPRs, spilling if needed); the plain ones let it use
-// the whole register file (one wave per SIMD for the FP64 path).
-template <typename T, int IP>
-__global__ __launch_bounds__(64) void k_trace(const TraceParams<T> *__restrict__ P) { trace_body<T, IP>(P); }
-template <typename T, int IP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-void k_trace_w2(const TraceParams<T> *__restrict__ P) { trace_body<T, IP>(P); }
-template <typename T, int IP>
-__global__ __launch_bounds__(64) void k_tail(const TraceParams<T> *__restrict__ P) { tail_body<T, IP>(P); }
-template <typename T, int IP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-void k_tail_w2(const TraceParams<T> *__restrict__ P) { tail_body<T, IP>(P); }
-
-}  // namespace
+#include "rtgd_kernels.h"
 
 // ===========================================================================
 // Host side
@@ -1863,14 +1316,17 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     const int tails[4] = {-2, -1, ctx->n_cu * 8, ctx->n_cu * 16};
     const int occs[2] = {1, 2};
     const int orders[2] = {1, 2};
+    // one untimed run, then the median of three
     auto time_opts = [&](rt_trace_opts o, double &ms) -> rt_status {
         o.results_mem = RT_MEM_DEVICE;
-        ms = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {     // first run warms caches and code
+        double t[3];
+        for (int rep = 0; rep < 4; ++rep) {
             rt_status s2 = rt_trace(ctx, grid, fan, &o, &r);
             if (s2 != RT_OK) return s2;
-            ms = rep ? std::min(ms, r.kernel_ms) : ms;
+            if (rep) t[rep - 1] = r.kernel_ms;
         }
+        std::sort(t, t + 3);
+        ms = t[1];
         return RT_OK;
     };
     double best = 1e300;
@@ -1896,6 +1352,11 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     }
     (void)hipFree(buf);
     if (st != RT_OK) return st;
+    // keep the library defaults unless a candidate is clearly faster
+    if (!(best < 0.98 * inf.default_ms)) {
+        best = inf.default_ms;
+        bv = TuneVal{0, 0, 0};
+    }
     inf.best_ms = best;
     tuned->tail_threshold = bv.tail_threshold;
     tuned->waves_per_simd = bv.waves_per_simd;

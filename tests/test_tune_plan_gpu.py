@@ -53,10 +53,9 @@ def test_autotune_choice_is_cached_and_result_neutral(rt, ctx, grid, wl, tmp_pat
     rt.tune_cache_clear()
     t = rt.autotune(ctx, grid, fan, precision="mixed", **kw)
     assert not t["from_cache"] and t["n_candidates"] == 16
-    assert t["waves_per_simd"] in (1, 2)
-    assert t["tail_threshold"] in (-2, -1) or t["tail_threshold"] % 8 == 0
-    assert t["ray_order"] in (1, 2)
-    assert 0 < t["best_ms"] <= 1.5 * t["default_ms"]
+    assert t["tail_threshold"] in (-2, -1, 0) or t["tail_threshold"] % 8 == 0
+    assert t["ray_order"] in (0, 1, 2) and t["waves_per_simd"] in (0, 1, 2)
+    assert 0 < t["best_ms"] <= t["default_ms"]
     t2 = rt.autotune(ctx, grid, fan, precision="mixed", **kw)
     assert t2["from_cache"] and (t2["tail_threshold"], t2["waves_per_simd"], t2["ray_order"]) == \
         (t["tail_threshold"], t["waves_per_simd"], t["ray_order"])
