@@ -292,9 +292,6 @@ void fill_grid_dev(const rt_grid *grid, GridDev<T> &g)
     g.n_lat = q.n_lat; g.n_lon = q.n_lon; g.n_h = q.n_h;
     g.lat0 = q.lat0_deg; g.lon0 = q.lon0_deg; g.h0 = q.h0_km;
     g.inv_dlat = 1.0 / q.dlat_deg; g.inv_dlon = 1.0 / q.dlon_deg; g.inv_dh = 1.0 / q.dh_km;
-    g.lat_hi = q.lat0_deg + (q.n_lat - 1) * q.dlat_deg;
-    g.lon_hi = q.lon0_deg + (q.n_lon - 1) * q.dlon_deg;
-    g.h_hi = q.h0_km + (q.n_h - 1) * q.dh_km;
     g.R = q.earth_radius_km;
 }
 
@@ -478,6 +475,7 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.east[0] = -std::sin(lo); P.east[1] = std::cos(lo); P.east[2] = 0.0;
     P.r0 = gq.earth_radius_km + fan->tx_h_km;
     P.step = opts->step_km;
+    P.step6 = opts->step_km / 6.0;
     P.max_group = opts->max_group_km;
     P.exit_h = opts->exit_h_km > 0 ? opts->exit_h_km : gq.h0_km + (gq.n_h - 1) * gq.dh_km;
     P.floor_h = gq.h0_km;

@@ -42,7 +42,6 @@ struct GridDev {
     int32_t n_lat, n_lon, n_h;
     double lat0, lon0, h0;      // first node (deg, deg, km)
     double inv_dlat, inv_dlon, inv_dh;
-    double lat_hi, lon_hi, h_hi;
     double R;                   // Earth radius, km
 };
 
@@ -134,15 +133,18 @@ __device__ __forceinline__ void weights4(T s, T w[4], T dw[4])
     for (int a = 0; a < 4; ++a) eval_piece<T, IP>(piece<T, IP>(a), s, w[a], dw[a]);
 }
 
-// Cell of one axis: t in index units, cell k = clamp(floor(t), 1, n-3),
-// local s = t - k (s in [-1, 2] at the edge cells).  fmax/fmin keep the
-// index in range even for a NaN coordinate.
-__device__ __forceinline__ int locate(double t, int n, double &s)
+// Cell of one axis from the index coordinate t = (c - c0) / dc: cell
+// k = clamp(floor(t), 1, n - 3) and local s = t - k, clamped to [-1, 2]
+// (the edge cells' range), which is t clamped to the box [0, n - 1].  A
+// clamped axis has a zero partial derivative.  k stays in range for any t,
+// NaN included (s is then clamped to -1).
+__device__ __forceinline__ int locate(double t, int n, double &s, bool &clamped)
 {
-    double f = floor(t);
-    f = fmin(fmax(f, 1.0), double(n - 3));
-    s = t - f;
-    return int(f);
+    const int k = min(max(int(floor(t)), 1), n - 3);
+    const double su = t - double(k);
+    s = fmin(fmax(su, -1.0), 2.0);
+    clamped = s != su;
+    return k;
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates.  On
@@ -170,20 +172,10 @@ __device__ __forceinline__ double rsqrt(double a)
 }
 __device__ __forceinline__ float rsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
 
-// sin and cos of theta0 + d from those of theta0, for a small increment d
-// (|d| <= 0.05 rad): Taylor series of sin d and cos d (error < d^9/9!) and
+// sin and cos of theta0 + d from those of theta0, for a small increment
+// |d| <= 2^-10 rad: the Taylor series of sin d and cos d, cut after the d^5
+// and d^6 terms (the first omitted terms are below 2e-25 and 3e-29), and
 // the angle-addition formulas.
-__device__ __forceinline__ void sincos_add(double s0, double c0, double d, double &s, double &c)
-{
-    double d2 = d * d;
-    double sd = d * fm(-d2 * (1.0 / 6.0), fm(-d2 * (1.0 / 20.0), fm(-d2, 1.0 / 42.0, 1.0), 1.0), 1.0);
-    double cd = fm(-d2 * 0.5,
-                   fm(-d2 * (1.0 / 12.0), fm(-d2 * (1.0 / 30.0), fm(-d2, 1.0 / 56.0, 1.0), 1.0), 1.0), 1.0);
-    s = fm(s0, cd, c0 * sd);
-    c = fm(c0, cd, -(s0 * sd));
-}
-// The same for |d| <= 2^-10, with the series cut after the d^5 (sine) and
-// d^6 (cosine) terms: the first omitted terms are below 2e-25 and 3e-29.
 __device__ __forceinline__ void sincos_add_small(double s0, double c0, double d, double &s, double &c)
 {
     double d2 = d * d;
@@ -273,19 +265,13 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
         Fr = Fth = Fph = T(0);
         return;
     }
-    double lat = fm(-th, kRad2Deg, 90.0);
-    double lon = ph * kRad2Deg;
-    bool cl = false, co = false, ch = false;
-    if (lat < g.lat0) { lat = g.lat0; cl = true; }
-    else if (lat > g.lat_hi) { lat = g.lat_hi; cl = true; }
-    if (lon < g.lon0) { lon = g.lon0; co = true; }
-    else if (lon > g.lon_hi) { lon = g.lon_hi; co = true; }
-    if (h > g.h_hi) { h = g.h_hi; ch = true; }
-
+    // index coordinates, clamped to the box through the local coordinates
+    // (selects, no branches)
     double sl_, so_, sh_;
-    int il = locate((lat - g.lat0) * g.inv_dlat, g.n_lat, sl_);
-    int jl = locate((lon - g.lon0) * g.inv_dlon, g.n_lon, so_);
-    int kh = locate((h - g.h0) * g.inv_dh, g.n_h, sh_);
+    bool cl, co, ch;
+    const int il = locate((fm(-th, kRad2Deg, 90.0) - g.lat0) * g.inv_dlat, g.n_lat, sl_, cl);
+    const int jl = locate((ph * kRad2Deg - g.lon0) * g.inv_dlon, g.n_lon, so_, co);
+    const int kh = locate((h - g.h0) * g.inv_dh, g.n_h, sh_, ch);
 
     const size_t nh = size_t(g.n_h);
     const size_t row = size_t(g.n_lon) * nh;
@@ -523,14 +509,18 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
     return isfinite(double(G)) && G != T(0);
 }
 
-// One fixed RK4 step of size h (always FP64 state and combination).  The
-// four stages share one copy of the right-hand side (stage loop, not
-// unrolled) to keep register pressure and code size down.  sin and cos of
-// the colatitude are evaluated once per step; the later stages, whose
-// colatitude differs by a small increment, use sincos_add.
-template <typename T, int IP, int LANES>
+// One fixed RK4 step of size h (always FP64 state and combination); h6 is
+// h / 6, rounded once by the caller.  UNROLL = false: the four stages share
+// one copy of the right-hand side (a stage loop), which keeps register
+// pressure and code size down where many rays share a wave; UNROLL = true
+// (the sixteen-lane tail, bound by the latency of one ray) drops the loop's
+// per-stage selects and copies.  The arithmetic is the same either way.
+// sin and cos of the colatitude are evaluated once per step; the later
+// stages, whose colatitude differs by a small increment (about 1e-4 rad at
+// 1 km steps), use sincos_add_small.
+template <typename T, int IP, int LANES, bool UNROLL = false>
 __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc, double y[7], double h,
-                                         StencilCache<T, LANES> &sc)
+                                         double h6, StencilCache<T, LANES> &sc)
 {
     double k[7], acc[7], t[7];
     bool ok = true;
@@ -538,14 +528,11 @@ __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc
     sincos(y[1], &s0, &c0);
 #pragma unroll
     for (int i = 0; i < 7; ++i) { t[i] = y[i]; acc[i] = 0.0; }
-#pragma unroll 1
-    for (int stage = 0; stage < 4; ++stage) {
+    auto stage_body = [&](int stage) {
         double st = s0, ct = c0;
         const double d = t[1] - y[1];
         if (stage > 0) {
-            const double ad = fabs(d);
-            if (ad <= 0x1p-10) sincos_add_small(s0, c0, d, st, ct);
-            else if (ad <= 0.05) sincos_add(s0, c0, d, st, ct);
+            if (fabs(d) <= 0x1p-10) sincos_add_small(s0, c0, d, st, ct);
             else sincos(t[1], &st, &ct);
         }
         ok &= ray_rhs<T, IP, LANES>(g, rc, t, T(st), T(ct), sc, k);
@@ -557,9 +544,16 @@ __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc
             acc[i] = fm(wgt, k[i], acc[i]);
             t[i] = fm(c, k[i], y[i]);
         }
+    };
+    if constexpr (UNROLL) {
+#pragma unroll
+        for (int stage = 0; stage < 4; ++stage) stage_body(stage);
+    } else {
+#pragma unroll 1
+        for (int stage = 0; stage < 4; ++stage) stage_body(stage);
     }
 #pragma unroll
-    for (int i = 0; i < 7; ++i) y[i] = fm(h / 6.0, acc[i], y[i]);
+    for (int i = 0; i < 7; ++i) y[i] = fm(h6, acc[i], y[i]);
     return ok;
 }
 

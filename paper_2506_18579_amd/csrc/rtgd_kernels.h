@@ -55,7 +55,8 @@ struct TraceParams {
     double tx_lon;             // rad
     double up[3], north[3], east[3];   // transmitter frame (Cartesian)
     double r0;                 // R + tx height
-    double step, max_group, exit_h, floor_h;
+    double step, step6;        // step and step / 6 (km)
+    double max_group, exit_h, floor_h;
     int32_t max_steps;         // hard cap (never reached before max_group)
     int32_t traj_stride;
     int64_t traj_per_ray;
@@ -254,11 +255,11 @@ __device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray, Lan
 // One RK4 step plus the termination tests.  Returns the ray status, or -1
 // if the ray goes on.  `write` is false on the lanes of a row that only
 // shadow the row's leader (no memory writes).
-template <typename T, int IP, int LANES>
+template <typename T, int IP, int LANES, bool UNROLL = false>
 __device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L, bool write,
                                        StencilCache<T, LANES> &sc)
 {
-    bool ok = rk4_step<T, IP, LANES>(P.g, L.rc, L.y, P.step, sc);
+    bool ok = rk4_step<T, IP, LANES, UNROLL>(P.g, L.rc, L.y, P.step, P.step6, sc);
     L.gp += P.step;
     ++L.steps;
     double h = L.y[0] - P.g.R;
@@ -331,7 +332,7 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred, int lane
 // and run identical arithmetic; only the stencil contraction is split (one
 // column per lane, see medium<T, IP, 16>), so the results equal the
 // one-lane kernel's bit for bit.  Lane 0 of the row writes.
-template <typename T, int IP>
+template <typename T, int IP, bool UNROLL>
 __device__ __forceinline__ void run_rows(const TraceParams<T> &P, int ray, Lane &L)
 {
     const int lane = int(__lane_id());
@@ -343,7 +344,7 @@ __device__ __forceinline__ void run_rows(const TraceParams<T> &P, int ray, Lane 
     for (;;) {
         if (__ballot(ray >= 0) == 0ull) break;
         if (ray >= 0) {
-            int st = advance<T, IP, 16>(P, ray, L, lead, sc);
+            int st = advance<T, IP, 16, UNROLL>(P, ray, L, lead, sc);
             if (st >= 0) {
                 if (lead) finish_ray(P, ray, L, st);
                 ray = -1;
@@ -472,7 +473,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
     // after the one-lane loop, so that its stencil cache is dead here
     if (to_rows) {
         gather_rows(to_rows, ray, L);
-        run_rows<T, IP>(P, ray, L);
+        run_rows<T, IP, false>(P, ray, L);
     }
 }
 
@@ -503,7 +504,7 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
         L.steps = H.steps;
         L.ntraj = H.ntraj;
     }
-    run_rows<T, IP>(P, ray, L);
+    run_rows<T, IP, true>(P, ray, L);
 }
 
 // Oblique-ionogram extraction: one thread per (frequency, mode) trace scans
