@@ -292,6 +292,7 @@ void fill_grid_dev(const rt_grid *grid, GridDev<T> &g)
     g.n_lat = q.n_lat; g.n_lon = q.n_lon; g.n_h = q.n_h;
     g.lat0 = q.lat0_deg; g.lon0 = q.lon0_deg; g.h0 = q.h0_km;
     g.inv_dlat = 1.0 / q.dlat_deg; g.inv_dlon = 1.0 / q.dlon_deg; g.inv_dh = 1.0 / q.dh_km;
+    g.kmax_lat = double(q.n_lat - 3); g.kmax_lon = double(q.n_lon - 3); g.kmax_h = double(q.n_h - 3);
     g.R = q.earth_radius_km;
 }
 
@@ -342,7 +343,7 @@ struct Counters {
 // (the hand-off buffer is device only): fan axes | segments | parameter
 // block | counters + per-segment steps | hand-off buffer.
 struct Layout {
-    size_t seg, par, cnt, steps, hand, host_bytes, dev_bytes;
+    size_t seg, par, cnt, steps, hand, rec, host_bytes, dev_bytes;
 };
 
 size_t fan_values(const rt_fan &f) { return size_t(f.n_elev) + f.n_az + f.n_freq; }
@@ -358,7 +359,8 @@ Layout job_layout(const TraceJob &j)
     L.steps = L.cnt + align_up(sizeof(Counters), 64);
     L.hand = L.steps + align_up(j.segs.size() * 8, 256);
     L.host_bytes = L.hand;
-    L.dev_bytes = L.hand + size_t(j.tail) * sizeof(Handoff) + 256;
+    L.rec = L.hand + align_up(size_t(j.tail) * sizeof(Handoff), 256);
+    L.dev_bytes = L.rec + size_t(j.n_rays) * sizeof(RayRec) + 256;
     return L;
 }
 
@@ -490,6 +492,7 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.live = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, live));
     P.n_handoff = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, n_handoff));
     P.handoff = reinterpret_cast<Handoff *>(dev + lay.hand);
+    P.rec = reinterpret_cast<RayRec *>(dev + lay.rec);
     P.handoff_threshold = job.tail;
     P.inwave = job.inwave;
     P.perm_stride = job.perm;
@@ -547,18 +550,31 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     const int occ = job.occ;
     const void *kt;
     const void *kl;
+    const void *ks;   // starting states
+    const void *kf;   // outputs
+    // the block goes to the kernels twice: by value (kernel arguments, for
+    // the trace loop) and in device memory (for the out-of-line calls)
+    TraceParams<float> Pf{};
+    TraceParams<double> Pd{};
+    void *pargs;
     if (mixed) {
-        TraceParams<float> P{};
+        TraceParams<float> &P = Pf;
         fill_params<float>(job, lay, P, dev);
         std::memcpy(host + lay.par, &P, sizeof(P));
+        pargs = &Pf;
+        ks = (const void *)k_start<float>;
+        kf = (const void *)k_finish<float>;
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<float, 1> : (const void *)k_trace_w2<float, 0>)
                       : (cr ? (const void *)k_trace<float, 1> : (const void *)k_trace<float, 0>);
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<float, 1> : (const void *)k_tail_w2<float, 0>)
                       : (cr ? (const void *)k_tail<float, 1> : (const void *)k_tail<float, 0>);
     } else {
-        TraceParams<double> P{};
+        TraceParams<double> &P = Pd;
         fill_params<double>(job, lay, P, dev);
         std::memcpy(host + lay.par, &P, sizeof(P));
+        pargs = &Pd;
+        ks = (const void *)k_start<double>;
+        kf = (const void *)k_finish<double>;
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<double, 1> : (const void *)k_trace_w2<double, 0>)
                       : (cr ? (const void *)k_trace<double, 1> : (const void *)k_trace<double, 0>);
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<double, 1> : (const void *)k_tail_w2<double, 0>)
@@ -568,11 +584,14 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     int max_waves = resident_waves<double>(ctx, kt);
     int waves = std::max(1, std::min((job.n_rays + 63) / 64, max_waves));
     void *arg = dev + lay.par;
-    void *args[] = {&arg};
+    void *args[] = {pargs, &arg};
+    const dim3 per_ray((job.n_rays + 63) / 64);
     if (ev0) HIP_OR_FAIL(ctx, hipEventRecord(ev0, stream));
+    HIP_OR_FAIL(ctx, hipLaunchKernel(ks, per_ray, dim3(64), args, 0, stream));
     HIP_OR_FAIL(ctx, hipLaunchKernel(kt, dim3(waves), dim3(64), args, 0, stream));
     if (job.tail > 0)
         HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 3) / 4), dim3(64), args, 0, stream));
+    HIP_OR_FAIL(ctx, hipLaunchKernel(kf, per_ray, dim3(64), args, 0, stream));
     if (ev1) HIP_OR_FAIL(ctx, hipEventRecord(ev1, stream));
     HIP_OR_FAIL(ctx, hipMemcpyAsync(readback ? readback : host + lay.cnt, dev + lay.cnt, lay.hand - lay.cnt,
                                     hipMemcpyDeviceToHost, stream));

@@ -42,6 +42,7 @@ struct GridDev {
     int32_t n_lat, n_lon, n_h;
     double lat0, lon0, h0;      // first node (deg, deg, km)
     double inv_dlat, inv_dlon, inv_dh;
+    double kmax_lat, kmax_lon, kmax_h;   // last cell of each axis: n - 3
     double R;                   // Earth radius, km
 };
 
@@ -134,17 +135,18 @@ __device__ __forceinline__ void weights4(T s, T w[4], T dw[4])
 }
 
 // Cell of one axis from the index coordinate t = (c - c0) / dc: cell
-// k = clamp(floor(t), 1, n - 3) and local s = t - k, clamped to [-1, 2]
-// (the edge cells' range), which is t clamped to the box [0, n - 1].  A
-// clamped axis has a zero partial derivative.  k stays in range for any t,
-// NaN included (s is then clamped to -1).
-__device__ __forceinline__ int locate(double t, int n, double &s, bool &clamped)
+// k = clamp(floor(t), 1, kmax) with kmax = n - 3, and local s = t - k,
+// clamped to [-1, 2] (the edge cells' range), which is t clamped to the box
+// [0, n - 1].  A clamped axis has a zero partial derivative.  The cell is
+// clamped before the conversion to int, so it is in range for any t, NaN
+// included (s is then clamped to -1).
+__device__ __forceinline__ int locate(double t, double kmax, double &s, bool &clamped)
 {
-    const int k = min(max(int(floor(t)), 1), n - 3);
-    const double su = t - double(k);
+    const double f = fmin(fmax(floor(t), 1.0), kmax);
+    const double su = t - f;
     s = fmin(fmax(su, -1.0), 2.0);
     clamped = s != su;
-    return k;
+    return int(f);
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates.  On
@@ -172,17 +174,30 @@ __device__ __forceinline__ double rsqrt(double a)
 }
 __device__ __forceinline__ float rsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
 
-// sin and cos of theta0 + d from those of theta0, for a small increment
-// |d| <= 2^-10 rad: the Taylor series of sin d and cos d, cut after the d^5
-// and d^6 terms (the first omitted terms are below 2e-25 and 3e-29), and
-// the angle-addition formulas.
-__device__ __forceinline__ void sincos_add_small(double s0, double c0, double d, double &s, double &c)
+// sin and cos of theta0 + d from those of theta0, for |d| <= 0.05 rad: the
+// Taylor series of sin d (to d^7) and cos d (to d^8), whose first omitted
+// terms are below 6e-18 and 3e-20, and the angle-addition formulas.
+__device__ __forceinline__ void sincos_add(double s0, double c0, double d, double &s, double &c)
 {
     double d2 = d * d;
-    double sd = d * fm(-d2 * (1.0 / 6.0), fm(-d2, 1.0 / 20.0, 1.0), 1.0);
-    double cd = fm(-d2 * 0.5, fm(-d2 * (1.0 / 12.0), fm(-d2, 1.0 / 30.0, 1.0), 1.0), 1.0);
+    double sd = d * fm(-d2 * (1.0 / 6.0), fm(-d2 * (1.0 / 20.0), fm(-d2, 1.0 / 42.0, 1.0), 1.0), 1.0);
+    double cd = fm(-d2 * 0.5,
+                   fm(-d2 * (1.0 / 12.0), fm(-d2 * (1.0 / 30.0), fm(-d2, 1.0 / 56.0, 1.0), 1.0), 1.0), 1.0);
     s = fm(s0, cd, c0 * sd);
     c = fm(c0, cd, -(s0 * sd));
+}
+
+// The library's sin and cos, kept out of line: it runs rarely (a new
+// anchor, below), and inlined its many constants would hold registers for
+// the whole trace loop.
+struct SinCos {
+    double s, c;
+};
+__device__ __attribute__((noinline)) SinCos sincos_ref(double x)
+{
+    SinCos r;
+    sincos(x, &r.s, &r.c);
+    return r;
 }
 
 // Cross-lane exchange through DPP (no LDS round trip), on the two 32-bit
@@ -269,9 +284,9 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
     // (selects, no branches)
     double sl_, so_, sh_;
     bool cl, co, ch;
-    const int il = locate((fm(-th, kRad2Deg, 90.0) - g.lat0) * g.inv_dlat, g.n_lat, sl_, cl);
-    const int jl = locate((ph * kRad2Deg - g.lon0) * g.inv_dlon, g.n_lon, so_, co);
-    const int kh = locate((h - g.h0) * g.inv_dh, g.n_h, sh_, ch);
+    const int il = locate((fm(-th, kRad2Deg, 90.0) - g.lat0) * g.inv_dlat, g.kmax_lat, sl_, cl);
+    const int jl = locate((ph * kRad2Deg - g.lon0) * g.inv_dlon, g.kmax_lon, so_, co);
+    const int kh = locate((h - g.h0) * g.inv_dh, g.kmax_h, sh_, ch);
 
     const size_t nh = size_t(g.n_h);
     const size_t row = size_t(g.n_lon) * nh;
@@ -305,7 +320,10 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
     // between large node values where the density varies little across the
     // cell.
     T uref = T(0);
-    if constexpr (sizeof(T) == 4) uref = (LANES == 1) ? sc.u[1][1][1] : sc.uref;
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (LANES == 1) uref = sc.u[1][1][1];
+        else uref = sc.uref;
+    }
 
     T v, glat, glon, gh;
     if constexpr (LANES == 1) {
@@ -509,31 +527,50 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
     return isfinite(double(G)) && G != T(0);
 }
 
+// Anchor of a ray's colatitude: th and its sin and cos from the library.
+// Every stage takes sin and cos of its colatitude from the anchor with
+// sincos_add, so that the library is needed only when the ray has moved
+// far from the anchor (see rk4_step).
+struct Anchor {
+    double th, s, c;
+};
+constexpr double kAnchorMove = 0.025;   // re-anchor beyond this (rad)
+constexpr double kSeriesMax = 0.05;     // range of sincos_add (rad)
+
+__device__ __forceinline__ Anchor make_anchor(double th)
+{
+    const SinCos q = sincos_ref(th);
+    return Anchor{th, q.s, q.c};
+}
+
 // One fixed RK4 step of size h (always FP64 state and combination); h6 is
 // h / 6, rounded once by the caller.  UNROLL = false: the four stages share
 // one copy of the right-hand side (a stage loop), which keeps register
 // pressure and code size down where many rays share a wave; UNROLL = true
 // (the sixteen-lane tail, bound by the latency of one ray) drops the loop's
 // per-stage selects and copies.  The arithmetic is the same either way.
-// sin and cos of the colatitude are evaluated once per step; the later
-// stages, whose colatitude differs by a small increment (about 1e-4 rad at
-// 1 km steps), use sincos_add_small.
+// The anchor moves to the step's starting colatitude when that is more than
+// kAnchorMove from it (every 160 km or more of north-south travel), so that
+// every stage is within kSeriesMax of it for steps up to about 150 km; a
+// stage beyond that uses the library.
 template <typename T, int IP, int LANES, bool UNROLL = false>
 __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc, double y[7], double h,
-                                         double h6, StencilCache<T, LANES> &sc)
+                                         double h6, Anchor &an, StencilCache<T, LANES> &sc)
 {
     double k[7], acc[7], t[7];
     bool ok = true;
-    double s0, c0;
-    sincos(y[1], &s0, &c0);
+    if (!(fabs(y[1] - an.th) <= kAnchorMove)) an = make_anchor(y[1]);
 #pragma unroll
     for (int i = 0; i < 7; ++i) { t[i] = y[i]; acc[i] = 0.0; }
     auto stage_body = [&](int stage) {
-        double st = s0, ct = c0;
-        const double d = t[1] - y[1];
-        if (stage > 0) {
-            if (fabs(d) <= 0x1p-10) sincos_add_small(s0, c0, d, st, ct);
-            else sincos(t[1], &st, &ct);
+        const double d = t[1] - an.th;
+        double st, ct;
+        if (fabs(d) <= kSeriesMax) {
+            sincos_add(an.s, an.c, d, st, ct);
+        } else {
+            const SinCos q = sincos_ref(t[1]);
+            st = q.s;
+            ct = q.c;
         }
         ok &= ray_rhs<T, IP, LANES>(g, rc, t, T(st), T(ct), sc, k);
         // weights 1, 2, 2, 1 of the combination; next stage at y + c h k

@@ -60,6 +60,7 @@ struct TraceParams {
     int32_t max_steps;         // hard cap (never reached before max_group)
     int32_t traj_stride;
     int64_t traj_per_ray;
+    struct RayRec *rec;        // per launch ray: starting, then final state
     double *traj;              // trajectories, indexed by launch ray (one segment only)
     int32_t *traj_count;
     // scheduling
@@ -79,6 +80,7 @@ struct TraceParams {
 struct Handoff {
     double y[7];
     double gp, apogee;
+    Anchor an;
     int32_t ray, steps, ntraj, pad;
 };
 
@@ -138,10 +140,22 @@ struct Lane {
     double apogee;
     double az0;           // launch azimuth (deg)
     RayConst rc;
+    Anchor an;            // colatitude anchor (sin and cos of the stages)
     int32_t steps;
     int32_t ntraj;
     int32_t seg;          // segment of the ray
     int32_t local;        // ray index within the segment
+};
+
+// Per launch ray, in device memory: the starting state, written by k_start
+// before the trace kernels run, and, once the ray has terminated, its final
+// state and status, written by the trace kernels and turned into the ray's
+// outputs by k_finish.  Keeping launch and landing geometry (library
+// sin, cos, atan2, sqrt) out of the trace loop keeps that loop's registers
+// for the step itself.
+struct RayRec {
+    Lane L;
+    int32_t status, pad;
 };
 
 template <typename T>
@@ -211,16 +225,46 @@ __device__ __forceinline__ void init_ray(const TraceParams<T> &P, int ray, Lane 
     L.y[6] = s;
     L.gp = s;
     L.apogee = L.y[0] - P.g.R;
+    L.an = make_anchor(L.y[1]);
     L.steps = 0;
     L.ntraj = 0;
     if (P.traj_stride > 0 && write) put_traj(P, ray, L);
 }
 
-// Outputs of a terminated ray: landing (or sub-ray) point, ground range,
-// azimuth deviation (Sec. II-C outputs, plus the phase path).
-template <typename T>
-__device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray, Lane &L, int status)
+// Below the grid bottom and descending, a ray leaves along the straight
+// vacuum line through its point.  In spherical terms (x.d = r n_r / |n|,
+// |x|^2 = r^2) the line reaches r = R if disc = (x.d)^2 - (r^2 - R^2) >= 0,
+// after a distance s = (r^2 - R^2) / (-x.d + sqrt(disc)).
+__device__ __forceinline__ double vacuum_disc(const double y[7], double R, double &xd, double &c)
 {
+    xd = y[0] * y[3] * rtgd::rsqrt(fm(y[3], y[3], fm(y[4], y[4], y[5] * y[5])));
+    c = fm(y[0], y[0], -R * R);
+    return fm(xd, xd, -c);
+}
+
+// Outputs of a terminated ray (one thread per launch ray, from its final
+// state): a ground return first follows the vacuum line to the ground; then
+// the landing (or sub-ray) point, ground range and azimuth deviation
+// (Sec. II-C outputs, plus the phase path).
+template <typename T>
+__device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray)
+{
+    const RayRec &rec = P.rec[ray];
+    Lane L = rec.L;
+    const int status = rec.status;
+    if (status == kGround) {
+        double xd, c, x[3], d[3];
+        const double disc = vacuum_disc(L.y, P.g.R, xd, c);
+        const double s = c / (-xd + sqrt(fmax(disc, 0.0)));
+        state_to_cart(L.y, x, d);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x[i] += s * d[i];
+        L.gp += s;
+        L.y[6] += s;
+        L.y[0] = sqrt(dot3(x, x));
+        L.y[1] = atan2(sqrt(x[0] * x[0] + x[1] * x[1]), x[2]);
+        L.y[2] = lon_near(x[0], x[1], P.tx_lon);
+    }
     double st, ct, sp, cp;
     sincos(L.y[1], &st, &ct);
     sincos(L.y[2], &sp, &cp);
@@ -252,40 +296,73 @@ __device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray, Lan
     if (P.traj_count) P.traj_count[ray] = L.ntraj;
 }
 
+// A terminated ray's final state into its record (the fields a step changes).
+template <typename T>
+__device__ __forceinline__ void retire(const TraceParams<T> &P, int ray, const Lane &L, int status)
+{
+    RayRec &rec = P.rec[ray];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) rec.L.y[i] = L.y[i];
+    rec.L.gp = L.gp;
+    rec.L.apogee = L.apogee;
+    rec.L.steps = L.steps;
+    rec.L.ntraj = L.ntraj;
+    rec.status = status;
+}
+
+// A ray below the grid bottom whose vacuum line misses the Earth: it is
+// followed back up to the grid bottom and the ray goes on.  The trajectory
+// point of the step is recorded first, as for any other step.  Out of line
+// (rare).
+template <typename T>
+__device__ __attribute__((noinline)) Lane graze_back(const TraceParams<T> *Pp, int ray, Lane L, bool write)
+{
+    const TraceParams<T> &P = *Pp;
+    double x[3], d[3];
+    state_to_cart(L.y, x, d);
+    const double xd = dot3(x, d);
+    const double rb = P.g.R + P.floor_h;
+    const double c2 = dot3(x, x) - rb * rb;
+    const double s = -xd + sqrt(xd * xd - c2);
+    if (P.traj_stride > 0 && write && L.steps % P.traj_stride == 0) put_traj(P, ray, L);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x[i] += s * d[i];
+    L.gp += s;
+    const double ph = L.y[6] + s;
+    cart_to_state(x, d, P.tx_lon, L.y);
+    L.y[6] = ph;
+    return L;
+}
+
 // One RK4 step plus the termination tests.  Returns the ray status, or -1
 // if the ray goes on.  `write` is false on the lanes of a row that only
-// shadow the row's leader (no memory writes).
+// shadow the row's leader (no memory writes).  P is the caller's copy of
+// the parameter block (in registers), Pp the block itself (for the
+// out-of-line calls).
 template <typename T, int IP, int LANES, bool UNROLL = false>
-__device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L, bool write,
-                                       StencilCache<T, LANES> &sc)
+__device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParams<T> *Pp, int ray, Lane &L,
+                                       bool write, StencilCache<T, LANES> &sc)
 {
-    bool ok = rk4_step<T, IP, LANES, UNROLL>(P.g, L.rc, L.y, P.step, P.step6, sc);
+    bool ok = rk4_step<T, IP, LANES, UNROLL>(P.g, L.rc, L.y, P.step, P.step6, L.an, sc);
     L.gp += P.step;
     ++L.steps;
-    double h = L.y[0] - P.g.R;
+    const double h = L.y[0] - P.g.R;
     int status = -1;
-    int graze = 0;
-    double x[3], d[3], s = 0.0;
     bool finite = ok;
 #pragma unroll
     for (int i = 0; i < 7; ++i) finite = finite && isfinite(L.y[i]);
     if (!finite) {
         status = kNumeric;
     } else if (h < P.floor_h && L.y[3] < 0.0) {
-        // below the grid bottom and descending: vacuum line to r = R
-        state_to_cart(L.y, x, d);
-        double xd = dot3(x, d);
-        double c = dot3(x, x) - P.g.R * P.g.R;
-        double disc = xd * xd - c;
-        if (disc >= 0.0) {
-            s = c / (-xd + sqrt(disc));
+        // below the grid bottom and descending: a ground return (k_finish
+        // follows the vacuum line) unless the line misses the Earth
+        double xd, c;
+        if (vacuum_disc(L.y, P.g.R, xd, c) >= 0.0) {
             status = kGround;
         } else {
-            // grazing line missing the Earth: back up to the grid bottom
-            double rb = P.g.R + P.floor_h;
-            double c2 = dot3(x, x) - rb * rb;
-            s = -xd + sqrt(xd * xd - c2);
-            graze = 1;
+            if (h > L.apogee) L.apogee = h;
+            L = graze_back(Pp, ray, L, write);
+            return -1;
         }
     } else if (h >= P.exit_h) {
         status = kEscape;
@@ -294,23 +371,6 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, int ray, Lane &L
     }
     if (status != kNumeric && h > L.apogee) L.apogee = h;
     if (P.traj_stride > 0 && write && (L.steps % P.traj_stride == 0 || status >= 0)) put_traj(P, ray, L);
-
-    if (status == kGround) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) x[i] += s * d[i];
-        L.gp += s;
-        L.y[6] += s;
-        L.y[0] = sqrt(dot3(x, x));
-        L.y[1] = atan2(sqrt(x[0] * x[0] + x[1] * x[1]), x[2]);
-        L.y[2] = lon_near(x[0], x[1], P.tx_lon);
-    } else if (graze) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) x[i] += s * d[i];
-        L.gp += s;
-        double ph = L.y[6] + s;
-        cart_to_state(x, d, P.tx_lon, L.y);
-        L.y[6] = ph;
-    }
     return status;
 }
 
@@ -333,7 +393,7 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred, int lane
 // column per lane, see medium<T, IP, 16>), so the results equal the
 // one-lane kernel's bit for bit.  Lane 0 of the row writes.
 template <typename T, int IP, bool UNROLL>
-__device__ __forceinline__ void run_rows(const TraceParams<T> &P, int ray, Lane &L)
+__device__ __forceinline__ void run_rows(const TraceParams<T> &P, const TraceParams<T> *Pp, int ray, Lane &L)
 {
     const int lane = int(__lane_id());
     const bool lead = (lane & 15) == 0;
@@ -344,9 +404,9 @@ __device__ __forceinline__ void run_rows(const TraceParams<T> &P, int ray, Lane 
     for (;;) {
         if (__ballot(ray >= 0) == 0ull) break;
         if (ray >= 0) {
-            int st = advance<T, IP, 16, UNROLL>(P, ray, L, lead, sc);
+            int st = advance<T, IP, 16, UNROLL>(P, Pp, ray, L, lead, sc);
             if (st >= 0) {
-                if (lead) finish_ray(P, ray, L, st);
+                if (lead) retire(P, ray, L, st);
                 ray = -1;
             }
         }
@@ -371,6 +431,9 @@ __device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, L
     for (int i = 0; i < 7; ++i) M.y[i] = __shfl(L.y[i], s);
     M.gp = __shfl(L.gp, s);
     M.apogee = __shfl(L.apogee, s);
+    M.an.th = __shfl(L.an.th, s);
+    M.an.s = __shfl(L.an.s, s);
+    M.an.c = __shfl(L.an.c, s);
     M.az0 = __shfl(L.az0, s);
     M.rc.v = reinterpret_cast<const void *>(
         __shfl((unsigned long long)reinterpret_cast<uintptr_t>(L.rc.v), s));
@@ -400,9 +463,8 @@ __device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, L
 // Every ray terminates (the group path grows by one step per iteration up
 // to max_group), so every wave exits.
 template <typename T, int IP>
-__device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp)
+__device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceParams<T> *__restrict__ Pp)
 {
-    const TraceParams<T> &P = *Pp;
     const int lane = int(__lane_id());
     int ray = -1;            // -1 idle, -2 queue drained, >= 0 live ray
     bool drained = false;
@@ -418,7 +480,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
                 if (q < P.n_rays) {
                     ray = int((unsigned long long)q * (unsigned long long)P.perm_stride %
                               (unsigned long long)P.n_rays);
-                    init_ray(P, ray, L, true);
+                    L = P.rec[ray].L;
                 } else {
                     ray = -2;
                 }
@@ -448,6 +510,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
                     for (int i = 0; i < 7; ++i) H.y[i] = L.y[i];
                     H.gp = L.gp;
                     H.apogee = L.apogee;
+                    H.an = L.an;
                     H.ray = ray;
                     H.steps = L.steps;
                     H.ntraj = L.ntraj;
@@ -461,9 +524,9 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
         }
         int st = -1;
         if (ray >= 0) {
-            st = advance<T, IP, 1>(P, ray, L, true, sc);
+            st = advance<T, IP, 1>(P, Pp, ray, L, true, sc);
             if (st >= 0) {
-                finish_ray(P, ray, L, st);
+                retire(P, ray, L, st);
                 ray = -1;
             }
         }
@@ -473,7 +536,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
     // after the one-lane loop, so that its stencil cache is dead here
     if (to_rows) {
         gather_rows(to_rows, ray, L);
-        run_rows<T, IP, false>(P, ray, L);
+        run_rows<T, IP, false>(P, Pp, ray, L);
     }
 }
 
@@ -484,9 +547,8 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> *__restrict__ Pp
 // bit.  Lane 0 of the row writes.  Launched with enough rows for the
 // hand-off capacity; rows past the number of records exit at once.
 template <typename T, int IP>
-__device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
+__device__ __forceinline__ void tail_body(const TraceParams<T> &P, const TraceParams<T> *__restrict__ Pp)
 {
-    const TraceParams<T> &P = *Pp;
     const int lane = int(__lane_id());
     const int slot = int(blockIdx.x) * 4 + (lane >> 4);
     const int n = *P.n_handoff;
@@ -495,16 +557,38 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> *__restrict__ Pp)
     if (slot < n) {
         const Handoff &H = P.handoff[slot];
         ray = H.ray;
-        double elev_unused;
-        ray_const(P, ray, L, elev_unused);
+        L = P.rec[ray].L;   // per-ray constants
 #pragma unroll
         for (int i = 0; i < 7; ++i) L.y[i] = H.y[i];
         L.gp = H.gp;
         L.apogee = H.apogee;
+        L.an = H.an;
         L.steps = H.steps;
         L.ntraj = H.ntraj;
     }
-    run_rows<T, IP, true>(P, ray, L);
+    run_rows<T, IP, true>(P, Pp, ray, L);
+}
+
+// Starting state of every launch ray (one thread per ray).
+template <typename T>
+__device__ __forceinline__ void start_body(const TraceParams<T> &P)
+{
+    const int ray = int(blockIdx.x) * 64 + int(threadIdx.x);
+    if (ray >= P.n_rays) return;
+    Lane L;
+    init_ray(P, ray, L, true);
+    RayRec &rec = P.rec[ray];
+    rec.L = L;
+    rec.status = -1;
+}
+
+// Outputs of every launch ray (one thread per ray), after the trace kernels.
+template <typename T>
+__device__ __forceinline__ void finish_body(const TraceParams<T> &P)
+{
+    const int ray = int(blockIdx.x) * 64 + int(threadIdx.x);
+    if (ray >= P.n_rays) return;
+    finish_ray(P, ray);
 }
 
 // Oblique-ionogram extraction: one thread per (frequency, mode) trace scans
@@ -549,15 +633,32 @@ __global__ __launch_bounds__(64) void k_ionogram(const double *__restrict__ elev
 // SIMD (at most 256 VGPRs, spilling if needed); the plain ones let it use
 // the whole register file (one wave per SIMD for the FP64 path).
 template <typename T, int IP>
-__global__ __launch_bounds__(64) void k_trace(const TraceParams<T> *__restrict__ P) { trace_body<T, IP>(P); }
+__global__ __launch_bounds__(64) void k_trace(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
+{
+    trace_body<T, IP>(P, Pp);
+}
 template <typename T, int IP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-void k_trace_w2(const TraceParams<T> *__restrict__ P) { trace_body<T, IP>(P); }
+void k_trace_w2(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
+{
+    trace_body<T, IP>(P, Pp);
+}
 template <typename T, int IP>
-__global__ __launch_bounds__(64) void k_tail(const TraceParams<T> *__restrict__ P) { tail_body<T, IP>(P); }
+__global__ __launch_bounds__(64) void k_tail(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
+{
+    tail_body<T, IP>(P, Pp);
+}
 template <typename T, int IP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-void k_tail_w2(const TraceParams<T> *__restrict__ P) { tail_body<T, IP>(P); }
+void k_tail_w2(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
+{
+    tail_body<T, IP>(P, Pp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_start(const TraceParams<T> P) { start_body<T>(P); }
+template <typename T>
+__global__ __launch_bounds__(64) void k_finish(const TraceParams<T> P) { finish_body<T>(P); }
 
 }  // namespace
 
