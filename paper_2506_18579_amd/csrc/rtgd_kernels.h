@@ -292,7 +292,6 @@ __device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray)
         if (S.out[k]) S.out[k][i] = o[k];
     if (S.status) S.status[i] = status;
     if (S.nsteps) S.nsteps[i] = L.steps;
-    atomicAdd(S.steps, (unsigned long long)L.steps);
     if (P.traj_count) P.traj_count[ray] = L.ntraj;
 }
 
@@ -582,13 +581,33 @@ __device__ __forceinline__ void start_body(const TraceParams<T> &P)
     rec.status = -1;
 }
 
-// Outputs of every launch ray (one thread per ray), after the trace kernels.
+// Outputs of every launch ray (one thread per ray), after the trace kernels,
+// and the RK4 step counts per segment: summed over the wave's lanes of each
+// segment first, so that there is one atomic per wave and segment rather
+// than one per ray on a single address.
 template <typename T>
 __device__ __forceinline__ void finish_body(const TraceParams<T> &P)
 {
     const int ray = int(blockIdx.x) * 64 + int(threadIdx.x);
-    if (ray >= P.n_rays) return;
-    finish_ray(P, ray);
+    const bool valid = ray < P.n_rays;
+    int seg = 0;
+    unsigned long long steps = 0;
+    if (valid) {
+        finish_ray(P, ray);
+        seg = P.rec[ray].L.seg;
+        steps = (unsigned long long)P.rec[ray].L.steps;
+    }
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int s0 = __shfl(seg, leader);
+        const bool mine = valid && seg == s0;
+        unsigned long long part = mine ? steps : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+        if (int(threadIdx.x) == leader) atomicAdd(P.seg[s0].steps, part);
+        todo &= ~__ballot(mine);
+    }
 }
 
 // Oblique-ionogram extraction: one thread per (frequency, mode) trace scans
