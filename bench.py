@@ -34,14 +34,15 @@ FLOPS_PER_STEP_ISO = 4 * 617 + 136
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (256 CU x 2.4 GHz x 128)
 PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 
-# HBM bytes of one FP64 ionogram launch (k_trace + k_tail) from rocprofv3:
-# FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB device copy
-# in the same runs).  Valid only for the device sources (per-step arithmetic
-# and trace kernels) with these hashes; otherwise reported as null.
-TRAFFIC_BYTES = (38646 + 23478) * 1024
+# HBM bytes of one FP64 ionogram launch (k_start, k_trace, k_tail and
+# k_finish) from rocprofv3: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors
+# from a 1 GiB device copy in the same runs).  Valid only for the device
+# sources (per-step arithmetic and trace kernels) with these hashes;
+# otherwise reported as null.
+TRAFFIC_BYTES = (71367 + 45516) * 1024
 TRAFFIC_SOURCES = {
-    "rtgd_device.h": "e0567561595ae14abf0a5581df28a5f9300abfeaf5f553c71285b4d5b575fb24",
-    "rtgd_kernels.h": "a7ca94f2b242d5d80b9cd2056156fb759c94ee2006426a0cc0d341e50b744969",
+    "rtgd_device.h": "fc2671d864d65019d61ee6dcdc3f5df412c22267d5495bb45054fd1589ddab48",
+    "rtgd_kernels.h": "96a5176bcf12c6a69aa89bc22e0138a08927826f503426b19256adf70691b102",
 }
 
 
@@ -274,14 +275,14 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS,
                      "traffic": measured_traffic(),
-                     "kernel": "trace launch: k_trace<double,0> + k_tail<double,0>",
+                     "kernel": "trace launch: k_start + k_trace<double,0> + k_tail<double,0> + k_finish",
                      "kernel_ms_avg": kms, "flops_per_ray_step": FLOPS_PER_STEP_ANISO},
         "tuning": {"fp64": tune64, "mixed": tune32},
         "cpu_baseline": cpu,
         "cpu_oracle_1thread": cpu_1thread,
         "end_to_end_host_results": {"ms_per_sweep": e2e_ms,
                                     "ray_steps_per_s": e2e[-1][1] / (e2e_ms * 1e-3),
-                                    "note": "fan upload, both kernels and the 8 MB result copy "
+                                    "note": "fan upload, the four kernels and the 8 MB result copy "
                                             "to pageable host memory"},
         "accuracy": accuracy,
         "mixed": {"value": mixed["ray_steps"] / mixed["elapsed"],

@@ -160,7 +160,7 @@ typedef struct {
     double *traj;
     int32_t *traj_count;
     int64_t total_steps;    /* out: sum of n_steps over the fan            */
-    double kernel_ms;       /* out: device time of the integration kernels */
+    double kernel_ms;       /* out: device time of the launch's kernels    */
 } rt_results;
 
 /* Create a context on HIP device `device` issuing work on `hip_stream`
@@ -277,8 +277,9 @@ rt_status rt_server_stats(const rt_server *srv, int32_t *queued, int32_t *runnin
 /* ------------------------------------------------------------------------
  * Replayable traces (HIP graph).  rt_plan_create validates a trace exactly
  * like rt_trace, stages its fan and parameter block once, and captures the
- * launch sequence (workspace upload, one-lane kernel, 16-lane tail
- * kernel, counter read-back) into a HIP graph on a private stream.  The
+ * launch sequence (workspace upload, ray-start kernel, one-lane kernel,
+ * 16-lane tail kernel, ray-finish kernel, counter read-back) into a HIP
+ * graph on a private stream.  The
  * plan owns its workspace and pinned staging; it borrows the grid and the
  * caller's result buffers, which must be device memory (opts->results_mem =
  * RT_MEM_DEVICE) and stay valid, like the grid, until rt_plan_destroy.
