@@ -83,6 +83,21 @@ def test_aniso_subfan_every_ray(rt, ctx, orc, aniso_wl, aniso_grid):
     assert len(rep["ill_conditioned"]) <= 3
 
 
+def test_long_steps_match_oracle(rt, ctx, orc, aniso_wl, aniso_grid):
+    """400 km RK4 steps: a stage's colatitude then lies beyond the range of the
+    series around the ray's anchor colatitude, so those stages take sin and cos
+    from the library; every ray still matches the oracle."""
+    fan = _subfan(aniso_wl)
+    g = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, step_km=400.0)
+    rays = fan.expand()
+    tr = oracle_tracer(orc, aniso_wl, fan, step=400.0)
+    o = tr(*rays)
+    rep = compare(g, o, rays, tr)
+    print("400 km steps worst rel err", rep["worst_rel"], "ill", len(rep["ill_conditioned"]),
+          "steps", int(g["n_steps"].sum()))
+    assert len(rep["ill_conditioned"]) <= 3
+
+
 def test_aniso_full_fan_sampled(rt, ctx, orc, aniso_wl, aniso_grid):
     """All 24,576 rays on the GPU (device-resident outputs, as benchmarked);
     a seeded sample of 160 checked against the oracle one by one."""
