@@ -46,6 +46,10 @@ TRAFFIC_SOURCES = {
 }
 
 
+# launch settings the autotuner chooses (results do not depend on them)
+TUNED_KNOBS = ("tail_threshold", "waves_per_simd", "ray_order", "promote_waves", "promote_age")
+
+
 def measured_traffic():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2506_18579_amd", "csrc")
@@ -71,8 +75,7 @@ def parse():
 
 def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup, tune=None):
     out = None
-    kw = dict(tail_threshold=tune["tail_threshold"], waves_per_simd=tune["waves_per_simd"],
-              ray_order=tune["ray_order"]) if tune else {}
+    kw = {k: tune[k] for k in TUNED_KNOBS} if tune else {}
     for _ in range(warmup):
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
                          exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out, **kw)
@@ -115,8 +118,7 @@ def main():
     for _ in range(3):
         t = time.perf_counter()
         r = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
-                       exit_h_km=wl.exit_km, precision="fp64", tail_threshold=tune64["tail_threshold"],
-                       waves_per_simd=tune64["waves_per_simd"], ray_order=tune64["ray_order"])
+                       exit_h_km=wl.exit_km, precision="fp64", **{k: tune64[k] for k in TUNED_KNOBS})
         e2e.append((time.perf_counter() - t, r["total_steps"]))
     e2e_ms = float(np.median([x[0] for x in e2e])) * 1e3
     fan_wl = synth.aniso_fan_workload(0)

@@ -133,6 +133,16 @@ typedef struct {
                                coprime to n_rays near 0.618 n_rays, which
                                spreads neighbouring (similar) rays over
                                many waves                                  */
+    int32_t promote_waves;  /* scheduling knob, results unchanged: this many
+                               waves run rays 16 lanes each beside the
+                               one-lane waves, taking over rays trapped in a
+                               duct (wave normal turning upward inside the
+                               ionosphere: they run to max_group_km) and rays
+                               older than promote_age steps; 0 = default
+                               (none), -1 = none, at most 64; ignored with
+                               tail_threshold = -2                         */
+    int32_t promote_age;    /* steps after which any ray may be promoted;
+                               0 = default (1500), -1 = trapped rays only  */
 } rt_trace_opts;
 
 /* Per-ray outputs, arrays of N_r = rt_fan_count() elements, owned by the
@@ -299,13 +309,15 @@ void rt_plan_destroy(rt_plan *plan);
 
 /* ------------------------------------------------------------------------
  * Autotuner.  The launch settings that change speed but not results are
- * tail_threshold, waves_per_simd and ray_order (see rt_trace_opts).
- * rt_autotune traces the given fan for every candidate setting
- * (tail_threshold in {-2, -1, 8 and 16 rays per CU} x waves_per_simd
- * in {1, 2} x ray_order in {index, strided}; one untimed run, then the
- * median device time of three), keeps the fastest if it beats the library
- * defaults by at least 2 % (else the defaults, all three fields 0) and
- * writes base with those three fields replaced to *tuned.  Choices are cached in the process under a key made of the
+ * tail_threshold, waves_per_simd, ray_order, promote_waves and promote_age
+ * (see rt_trace_opts).  rt_autotune traces the given fan for every
+ * candidate setting (tail_threshold in {-2, -1, 8 and 16 rays per CU} x
+ * waves_per_simd in {1, 2} x ray_order in {index, strided}; then, on top of
+ * the fastest of those unless it is the in-wave switch, (promote_waves,
+ * promote_age) in {(16, trapped rays only), (16, 3000), (32, 3000)}; one
+ * untimed run, then the median device time of three), keeps the fastest if
+ * it beats the library defaults by at least 2 % (else the defaults, all
+ * five fields 0) and writes base with those five fields replaced to *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on
  * or off and the ray count rounded to a power of two; a cached key is
  * answered without tracing.  Results of the trial traces are discarded

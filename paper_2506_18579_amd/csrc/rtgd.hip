@@ -325,6 +325,8 @@ struct TraceJob {
     int inwave = 0;            // in-wave switch to 16 lanes per ray
     int64_t perm = 1;          // visiting stride
     int occ = 1;               // register budget variant
+    int promote = 0;           // promotion waves (0: none)
+    int promote_age = 0;       // promote rays of at least this many steps too (0: trapped rays only)
     int32_t *tcount = nullptr;
     double *traj = nullptr;
     int64_t per_ray = 0;
@@ -333,17 +335,25 @@ struct TraceJob {
 static_assert(sizeof(TraceParams<float>) <= sizeof(TraceParams<double>),
               "the workspace reserves room for the FP64 parameter block");
 
+// Promotion waves (rt_trace_opts::promote_waves): at most, and the library
+// defaults (0: none; promote rays of at least 1500 steps besides trapped
+// ones).
+constexpr int kMaxPromoteWaves = 64;
+constexpr int kDefaultPromoteWaves = 0;
+constexpr int kDefaultPromoteAge = 1500;
+
 // Counters the kernels update, read back after a launch (followed by one
 // step counter per segment).
 struct Counters {
     int32_t head, trunc, live, n_handoff;
+    int32_t promo_push, promo_pop, promo_live, producers_alive, promo_err, pad;
 };
 
 // Workspace layout of a launch, the same on the device and in host staging
 // (the hand-off buffer is device only): fan axes | segments | parameter
 // block | counters + per-segment steps | hand-off buffer.
 struct Layout {
-    size_t seg, par, cnt, steps, hand, rec, host_bytes, dev_bytes;
+    size_t seg, par, cnt, steps, hand, rec, ids, host_bytes, dev_bytes;
 };
 
 size_t fan_values(const rt_fan &f) { return size_t(f.n_elev) + f.n_az + f.n_freq; }
@@ -360,7 +370,8 @@ Layout job_layout(const TraceJob &j)
     L.hand = L.steps + align_up(j.segs.size() * 8, 256);
     L.host_bytes = L.hand;
     L.rec = L.hand + align_up(size_t(j.tail) * sizeof(Handoff), 256);
-    L.dev_bytes = L.rec + size_t(j.n_rays) * sizeof(RayRec) + 256;
+    L.ids = L.rec + align_up(size_t(j.n_rays) * sizeof(RayRec), 256);
+    L.dev_bytes = L.ids + size_t(j.n_rays) * sizeof(int32_t) + 256;
     return L;
 }
 
@@ -389,6 +400,10 @@ rt_status validate_request(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
         return fail(ctx, RT_E_INVALID, "waves_per_simd must be 0, 1 or 2");
     if (opts->ray_order < 0 || opts->ray_order > 2)
         return fail(ctx, RT_E_INVALID, "ray_order must be 0, 1 or 2");
+    if (opts->promote_waves < -1 || opts->promote_waves > kMaxPromoteWaves)
+        return fail(ctx, RT_E_INVALID, "promote_waves must be in [-1, 64]");
+    if (opts->promote_age < -1)
+        return fail(ctx, RT_E_INVALID, "promote_age must be >= -1");
     if (opts->traj_stride < 0 || opts->traj_capacity < 0)
         return fail(ctx, RT_E_INVALID, "negative trajectory option");
     if (!(fan->tx_h_km >= 0.0) || !(fan->tx_h_km < gq.h0_km))
@@ -439,6 +454,10 @@ void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
     job.inwave = tail == -2 ? 1 : 0;
     job.tail = tail > 0 ? int(std::min<int64_t>(tail, n64)) : 0;
     job.perm = opts.ray_order == 2 ? visit_stride(n64) : 1;
+    // promotion runs beside the one-lane waves; not with the in-wave switch
+    const int pw = opts.promote_waves == 0 ? kDefaultPromoteWaves : opts.promote_waves;
+    job.promote = (pw > 0 && !job.inwave) ? pw : 0;
+    job.promote_age = opts.promote_age == 0 ? kDefaultPromoteAge : std::max(0, opts.promote_age);
     job.per_ray = opts.traj_stride > 0 && n64 > 0 ? opts.traj_capacity / n64 : 0;
 }
 
@@ -454,12 +473,14 @@ bool compatible(const JobSeg &a, const rt_trace_opts &oa, const JobSeg &b, const
            oa.step_km == ob.step_km && oa.max_group_km == ob.max_group_km &&
            oa.exit_h_km == ob.exit_h_km && oa.precision == ob.precision &&
            oa.tail_threshold == ob.tail_threshold && oa.waves_per_simd == ob.waves_per_simd &&
-           oa.ray_order == ob.ray_order &&
+           oa.ray_order == ob.ray_order && oa.promote_waves == ob.promote_waves &&
+           oa.promote_age == ob.promote_age &&
            oa.traj_stride == 0 && ob.traj_stride == 0;
 }
 
 template <typename T>
-void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char *dev)
+void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char *dev, int n_producers,
+                 int n_promote)
 {
     const JobSeg &s0 = job.segs[0];
     const rt_grid_geom &gq = s0.grid->geom;
@@ -493,6 +514,15 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.n_handoff = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, n_handoff));
     P.handoff = reinterpret_cast<Handoff *>(dev + lay.hand);
     P.rec = reinterpret_cast<RayRec *>(dev + lay.rec);
+    P.n_producers = n_producers;
+    P.promote_cap = 4 * n_promote;
+    P.promote_age = job.promote_age;
+    P.promo_push = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_push));
+    P.promo_pop = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_pop));
+    P.promo_live = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_live));
+    P.producers_alive = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, producers_alive));
+    P.promo_err = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_err));
+    P.promo_ids = reinterpret_cast<int32_t *>(dev + lay.ids);
     P.handoff_threshold = job.tail;
     P.inwave = job.inwave;
     P.perm_stride = job.perm;
@@ -543,25 +573,13 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         start += js.n_rays;
         off += fan_values(f);
     }
-    Counters hc{};
-    hc.live = job.n_rays;
-    std::memcpy(host + lay.cnt, &hc, sizeof(hc));
     const bool cr = job.segs[0].grid->geom.interp == RT_INTERP_CR;
     const int occ = job.occ;
     const void *kt;
     const void *kl;
     const void *ks;   // starting states
     const void *kf;   // outputs
-    // the block goes to the kernels twice: by value (kernel arguments, for
-    // the trace loop) and in device memory (for the out-of-line calls)
-    TraceParams<float> Pf{};
-    TraceParams<double> Pd{};
-    void *pargs;
     if (mixed) {
-        TraceParams<float> &P = Pf;
-        fill_params<float>(job, lay, P, dev);
-        std::memcpy(host + lay.par, &P, sizeof(P));
-        pargs = &Pf;
         ks = (const void *)k_start<float>;
         kf = (const void *)k_finish<float>;
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<float, 1> : (const void *)k_trace_w2<float, 0>)
@@ -569,10 +587,6 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<float, 1> : (const void *)k_tail_w2<float, 0>)
                       : (cr ? (const void *)k_tail<float, 1> : (const void *)k_tail<float, 0>);
     } else {
-        TraceParams<double> &P = Pd;
-        fill_params<double>(job, lay, P, dev);
-        std::memcpy(host + lay.par, &P, sizeof(P));
-        pargs = &Pd;
         ks = (const void *)k_start<double>;
         kf = (const void *)k_finish<double>;
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<double, 1> : (const void *)k_trace_w2<double, 0>)
@@ -580,9 +594,32 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<double, 1> : (const void *)k_tail_w2<double, 0>)
                       : (cr ? (const void *)k_tail<double, 1> : (const void *)k_tail<double, 0>);
     }
+    // One-lane waves first, promotion waves after them: blocks are
+    // dispatched in index order, so a promotion wave runs only once every
+    // one-lane wave is resident.  All of them fit at once on an idle GPU.
+    const int max_waves = resident_waves<double>(ctx, kt);
+    const int n_promote = job.promote > 0 && max_waves > 2 * job.promote ? job.promote : 0;
+    const int producers = std::max(1, std::min((job.n_rays + 63) / 64, max_waves - n_promote));
+    const int waves = producers + n_promote;
+    Counters hc{};
+    hc.live = job.n_rays;
+    hc.producers_alive = producers;
+    std::memcpy(host + lay.cnt, &hc, sizeof(hc));
+    // the block goes to the kernels twice: by value (kernel arguments, for
+    // the trace loop) and in device memory (for the out-of-line calls)
+    TraceParams<float> Pf{};
+    TraceParams<double> Pd{};
+    void *pargs;
+    if (mixed) {
+        fill_params<float>(job, lay, Pf, dev, producers, n_promote);
+        std::memcpy(host + lay.par, &Pf, sizeof(Pf));
+        pargs = &Pf;
+    } else {
+        fill_params<double>(job, lay, Pd, dev, producers, n_promote);
+        std::memcpy(host + lay.par, &Pd, sizeof(Pd));
+        pargs = &Pd;
+    }
     HIP_OR_FAIL(ctx, hipMemcpyAsync(dev, host, lay.host_bytes, hipMemcpyHostToDevice, stream));
-    int max_waves = resident_waves<double>(ctx, kt);
-    int waves = std::max(1, std::min((job.n_rays + 63) / 64, max_waves));
     void *arg = dev + lay.par;
     void *args[] = {pargs, &arg};
     const dim3 per_ray((job.n_rays + 63) / 64);
@@ -706,6 +743,7 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     job_counters(job, pinned, hc, steps);
     res->total_steps = steps[0];
     res->kernel_ms = ms;
+    if (hc.promo_err) return fail(ctx, RT_E_DEVICE, "promotion queue timed out");
     return hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
 }
 
@@ -1053,7 +1091,7 @@ extern "C" rt_status rt_server_poll(rt_server *srv, rt_request_info *done, int32
             Request &r = srv->reqs[sl.reqs[k]];
             r.info.total_steps = steps[k];
             r.info.kernel_ms = ms;
-            r.info.status = hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+            r.info.status = hc.promo_err ? RT_E_DEVICE : hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
             r.state = 2;
             if (r.cancelled) {
                 srv->arena.release(r.off, r.bytes);
@@ -1258,6 +1296,7 @@ extern "C" rt_status rt_plan_wait(rt_plan *p, int64_t *total_steps, double *kern
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, p->ev0, p->ev1));
     if (total_steps) *total_steps = steps[0];
     if (kernel_ms) *kernel_ms = ms;
+    if (hc.promo_err) return fail(ctx, RT_E_DEVICE, "promotion queue timed out");
     return RT_OK;
 }
 
@@ -1275,7 +1314,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int32_t tail_threshold, waves_per_simd, ray_order;
+    int32_t tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age;
 };
 
 std::mutex g_tune_mu;
@@ -1310,6 +1349,8 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
             tuned->tail_threshold = it->second.tail_threshold;
             tuned->waves_per_simd = it->second.waves_per_simd;
             tuned->ray_order = it->second.ray_order;
+            tuned->promote_waves = it->second.promote_waves;
+            tuned->promote_age = it->second.promote_age;
             inf.from_cache = 1;
             if (info) *info = inf;
             return RT_OK;
@@ -1347,11 +1388,13 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
         return RT_OK;
     };
     double best = 1e300;
-    TuneVal bv{0, 0, 0};
+    TuneVal bv{0, 0, 0, 0, 0};
     rt_trace_opts o = *base;
     o.tail_threshold = 0;
     o.waves_per_simd = 0;
     o.ray_order = 0;
+    o.promote_waves = 0;
+    o.promote_age = 0;
     st = time_opts(o, inf.default_ms);
     for (int oc : occs) {
         for (int tl : tails) {
@@ -1363,7 +1406,26 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
                 double ms = 0;
                 st = time_opts(o, ms);
                 ++inf.n_candidates;
-                if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od}; }
+                if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od, 0, 0}; }
+            }
+        }
+    }
+    // then promotion on top of the best of those (not with the in-wave switch)
+    const int promos[3][2] = {{16, -1}, {16, 3000}, {32, 3000}};
+    if (bv.tail_threshold != -2) {
+        for (const auto &pr : promos) {
+            if (st != RT_OK) break;
+            o.tail_threshold = bv.tail_threshold;
+            o.waves_per_simd = bv.waves_per_simd;
+            o.ray_order = bv.ray_order;
+            o.promote_waves = pr[0];
+            o.promote_age = pr[1];
+            double ms = 0;
+            st = time_opts(o, ms);
+            ++inf.n_candidates;
+            if (st == RT_OK && ms < best) {
+                best = ms;
+                bv = TuneVal{bv.tail_threshold, bv.waves_per_simd, bv.ray_order, pr[0], pr[1]};
             }
         }
     }
@@ -1372,12 +1434,14 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     // keep the library defaults unless a candidate is clearly faster
     if (!(best < 0.98 * inf.default_ms)) {
         best = inf.default_ms;
-        bv = TuneVal{0, 0, 0};
+        bv = TuneVal{0, 0, 0, 0, 0};
     }
     inf.best_ms = best;
     tuned->tail_threshold = bv.tail_threshold;
     tuned->waves_per_simd = bv.waves_per_simd;
     tuned->ray_order = bv.ray_order;
+    tuned->promote_waves = bv.promote_waves;
+    tuned->promote_age = bv.promote_age;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = bv;
@@ -1393,12 +1457,13 @@ extern "C" rt_status rt_tune_cache_save(const char *path)
     if (!f) return RT_E_INVALID;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     f << "# n_cu n_lat n_lon n_h interp precision field log2_rays -> tail_threshold waves_per_simd "
-         "ray_order\n";
+         "ray_order promote_waves promote_age\n";
     for (const auto &kv : g_tune_cache) {
         const TuneKey &k = kv.first;
         f << k.n_cu << ' ' << k.n_lat << ' ' << k.n_lon << ' ' << k.n_h << ' ' << k.interp << ' '
           << k.precision << ' ' << k.field << ' ' << k.log2_rays << ' ' << kv.second.tail_threshold << ' '
-          << kv.second.waves_per_simd << ' ' << kv.second.ray_order << '\n';
+          << kv.second.waves_per_simd << ' ' << kv.second.ray_order << ' ' << kv.second.promote_waves << ' '
+          << kv.second.promote_age << '\n';
     }
     return f.good() ? RT_OK : RT_E_INVALID;
 }
@@ -1416,13 +1481,14 @@ extern "C" rt_status rt_tune_cache_load(const char *path)
         TuneKey k{};
         TuneVal v{};
         if (!(ss >> k.n_cu >> k.n_lat >> k.n_lon >> k.n_h >> k.interp >> k.precision >> k.field >>
-              k.log2_rays >> v.tail_threshold >> v.waves_per_simd >> v.ray_order))
+              k.log2_rays >> v.tail_threshold >> v.waves_per_simd >> v.ray_order >> v.promote_waves >>
+              v.promote_age))
             return RT_E_INVALID;
         std::string rest;
         if (ss >> rest) return RT_E_INVALID;
         if (v.waves_per_simd < 0 || v.waves_per_simd > 2 || v.tail_threshold > (1 << 24) ||
-            v.tail_threshold < -2 ||
-            v.ray_order < 0 || v.ray_order > 2)
+            v.tail_threshold < -2 || v.ray_order < 0 || v.ray_order > 2 || v.promote_waves < -1 ||
+            v.promote_waves > kMaxPromoteWaves || v.promote_age < -1)
             return RT_E_INVALID;
         loaded[k] = v;
     }

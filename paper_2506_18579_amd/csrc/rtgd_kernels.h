@@ -74,6 +74,17 @@ struct TraceParams {
                                // also the hand-off buffer capacity
     int32_t inwave;            // a drained wave with <= 4 live rays finishes them 16 lanes each
     int64_t perm_stride;       // launch ray q is visited as (q * perm_stride) mod n_rays
+    // promotion: waves with block index >= n_producers run promoted rays
+    // sixteen lanes each while the other waves still run one lane per ray
+    int32_t n_producers;       // one-lane waves (all waves when promotion is off)
+    int32_t promote_cap;       // promoted rays running or queued at most (4 per promotion wave; 0: off)
+    int32_t promote_age;       // also promote rays of at least this many steps (0: trapped rays only)
+    int32_t *promo_push;       // tickets issued (promoted rays)
+    int32_t *promo_pop;        // tickets claimed by promotion waves
+    int32_t *promo_live;       // promoted rays not yet finished or handed off
+    int32_t *producers_alive;  // one-lane waves still running
+    int32_t *promo_err;        // claims that timed out (reported as a launch error)
+    int32_t *promo_ids;        // ray of each ticket, -1 until published (n_rays entries)
 };
 
 // State of a ray moved from the one-lane to the sixteen-lane kernel.
@@ -145,6 +156,8 @@ struct Lane {
     int32_t ntraj;
     int32_t seg;          // segment of the ray
     int32_t local;        // ray index within the segment
+    int32_t trapped;      // turned upward inside the ionosphere (a duct)
+    int32_t pad;
 };
 
 // Per launch ray, in device memory: the starting state, written by k_start
@@ -228,6 +241,8 @@ __device__ __forceinline__ void init_ray(const TraceParams<T> &P, int ray, Lane 
     L.an = make_anchor(L.y[1]);
     L.steps = 0;
     L.ntraj = 0;
+    L.trapped = 0;
+    L.pad = 0;
     if (P.traj_stride > 0 && write) put_traj(P, ray, L);
 }
 
@@ -342,10 +357,15 @@ template <typename T, int IP, int LANES, bool UNROLL = false>
 __device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParams<T> *Pp, int ray, Lane &L,
                                        bool write, StencilCache<T, LANES> &sc)
 {
+    const double nr0 = L.y[3];
     bool ok = rk4_step<T, IP, LANES, UNROLL>(P.g, L.rc, L.y, P.step, P.step6, L.an, sc);
     L.gp += P.step;
     ++L.steps;
     const double h = L.y[0] - P.g.R;
+    // a ray whose wave normal turns from downward to upward well above the
+    // grid bottom is trapped between layers: such rays run to the maximum
+    // group path (used to pick rays for promotion only)
+    if (nr0 < 0.0 && L.y[3] >= 0.0 && h > P.floor_h + 5.0) L.trapped = 1;
     int status = -1;
     bool finite = ok;
 #pragma unroll
@@ -443,9 +463,78 @@ __device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, L
     M.ntraj = __shfl(L.ntraj, s);
     M.seg = __shfl(L.seg, s);
     M.local = __shfl(L.local, s);
+    M.trapped = __shfl(L.trapped, s);
+    M.pad = 0;
     const int r = __shfl(ray, s);
     L = M;
     ray = src < 0 ? -1 : r;
+}
+
+// Promotion, producer side (a one-lane wave): lanes whose ray is trapped
+// in a duct, or at least promote_age steps old, move the ray to the
+// promotion queue while there is room: trapped rays may fill all
+// promote_cap places, old rays three quarters of them, so that trapped
+// rays (the longest) always find room.  The state goes to the ray's
+// record, a ticket is taken, and the ray index is published under the
+// ticket (release).  The lane then idles and refills from the launch queue.
+template <typename T>
+__device__ __forceinline__ int promote_room(const TraceParams<T> &P, unsigned long long cm, int cap, int lane)
+{
+    const int k = __popcll(cm);
+    int room = 0;
+    if (lane == 0 && k > 0) {
+        const int old = atomicAdd(P.promo_live, k);
+        room = min(k, max(0, cap - old));
+        if (room < k) atomicSub(P.promo_live, k - room);
+    }
+    return __shfl(room, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void promote(const TraceParams<T> &P, int &ray, const Lane &L, int lane)
+{
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const bool trap = ray >= 0 && L.trapped != 0;
+    const bool aged = ray >= 0 && L.trapped == 0 && P.promote_age > 0 && L.steps >= P.promote_age;
+    const unsigned long long tm = __ballot(trap), am = __ballot(aged);
+    if ((tm | am) == 0ull) return;
+    const int rt = promote_room(P, tm, P.promote_cap, lane);
+    const int ra = promote_room(P, am, P.promote_cap - P.promote_cap / 4, lane);
+    const bool go = (trap && __popcll(tm & below) < rt) || (aged && __popcll(am & below) < ra);
+    if (__ballot(go) == 0ull) return;
+    if (go) P.rec[ray].L = L;
+    const int t = wave_append(P.promo_push, go, lane);
+    if (go) {
+        __hip_atomic_store(&P.promo_ids[t], ray, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        ray = -1;
+    }
+}
+
+// Promotion, consumer side (one lane of a promotion wave's row): claim the
+// next ticket if one is issued and not yet claimed, and wait for its ray
+// index (the producer publishes it right after taking the ticket).  Returns
+// the ray, or -1 if there is nothing to claim.  Both waits are bounded; a
+// publication that does not arrive is counted in promo_err.
+template <typename T>
+__device__ __forceinline__ int claim_promoted(const TraceParams<T> &P)
+{
+    int p = __hip_atomic_load(P.promo_pop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int k = 0; k < 64; ++k) {
+        const int q = __hip_atomic_load(P.promo_push, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p >= q) return -1;
+        const int seen = atomicCAS(P.promo_pop, p, p + 1);
+        if (seen == p) {
+            for (int w = 0; w < (1 << 22); ++w) {
+                const int r = __hip_atomic_load(&P.promo_ids[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (r >= 0) return r;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            atomicAdd(P.promo_err, 1);
+            return -1;
+        }
+        p = seen;
+    }
+    return -1;
 }
 
 // Persistent one-lane-per-ray kernel.  Each 64-lane wave loops { refill
@@ -521,6 +610,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
                 break;
             }
         }
+        if (P.promote_cap > 0 && (iter & 7) == 0) promote(P, ray, L, lane);
         int st = -1;
         if (ray >= 0) {
             st = advance<T, IP, 1>(P, Pp, ray, L, true, sc);
@@ -532,6 +622,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
         unsigned long long fin = __ballot(st >= 0);
         if (lane == 0 && fin && P.handoff_threshold > 0) atomicSub(P.live, __popcll(fin));
     }
+    if (lane == 0 && P.promote_cap > 0) atomicSub(P.producers_alive, 1);
     // after the one-lane loop, so that its stencil cache is dead here
     if (to_rows) {
         gather_rows(to_rows, ray, L);
@@ -568,6 +659,113 @@ __device__ __forceinline__ void tail_body(const TraceParams<T> &P, const TracePa
     run_rows<T, IP, true>(P, Pp, ray, L);
 }
 
+// Hand the rays of the rows marked `pred` (row leaders) to the tail kernel;
+// returns how many (the same on every lane).
+__device__ __forceinline__ int handoff_rows(bool pred, int ray, const Lane &L, int32_t *n_handoff, Handoff *buf,
+                                            int lane)
+{
+    const int slot = wave_append(n_handoff, pred, lane);
+    if (pred) {
+        Handoff &H = buf[slot];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) H.y[i] = L.y[i];
+        H.gp = L.gp;
+        H.apogee = L.apogee;
+        H.an = L.an;
+        H.ray = ray;
+        H.steps = L.steps;
+        H.ntraj = L.ntraj;
+        H.pad = 0;
+    }
+    return __popcll(__ballot(pred));
+}
+
+// Promotion wave: four 16-lane rows (as in the tail kernel) run promoted
+// rays, each row claiming the next ticket when it is idle.  When the
+// launch-wide hand-off condition holds, the rows' rays, and any ray claimed
+// after that, go to the tail kernel instead.  The wave exits once no
+// one-lane wave is left and every ticket is claimed (one-lane waves always
+// finish, so this is reached); an idle wait with work still possible is
+// bounded and counted in promo_err if it runs out.
+template <typename T, int IP>
+__device__ __forceinline__ void promote_body(const TraceParams<T> &P, const TraceParams<T> *Pp)
+{
+    const int lane = int(__lane_id());
+    const int lead_lane = lane & ~15;
+    const bool lead = lane == lead_lane;
+    StencilCache<T, 16> sc;
+    sc.clear();
+    sc.pa = piece<T, IP>((lane >> 2) & 3);
+    sc.pb = piece<T, IP>(lane & 3);
+    int ray = -1;
+    Lane L;
+    bool closing = false;
+    int idle = 0;
+    for (int iter = 0;; ++iter) {
+        if (!closing && P.handoff_threshold > 0 && (iter & 7) == 0) {
+            int live = 0, head = 0;
+            if (lane == 0) {
+                live = __hip_atomic_load(P.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                head = __hip_atomic_load(P.queue_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            live = __shfl(live, 0);
+            head = __shfl(head, 0);
+            closing = head >= P.n_rays && live <= P.handoff_threshold;
+        }
+        // idle rows claim promoted rays
+        if (__ballot(ray < 0) != 0ull) {
+            int r = -1;
+            if (lead && ray < 0) r = claim_promoted(P);
+            r = __shfl(r, lead_lane);
+            if (r >= 0) {
+                ray = r;
+                L = P.rec[ray].L;
+                sc.clear();
+            }
+        }
+        if (closing) {
+            const int n = handoff_rows(lead && ray >= 0, ray, L, P.n_handoff, P.handoff, lane);
+            if (lane == 0 && n > 0) {
+                atomicSub(P.live, n);
+                atomicSub(P.promo_live, n);
+            }
+            ray = -1;
+        }
+        if (__ballot(ray >= 0) != 0ull) {
+            int st = -1;
+            if (ray >= 0) {
+                st = advance<T, IP, 16, true>(P, Pp, ray, L, lead, sc);
+                if (st >= 0) {
+                    if (lead) retire(P, ray, L, st);
+                    ray = -1;
+                }
+            }
+            const int n = __popcll(__ballot(lead && st >= 0));
+            if (lane == 0 && n > 0) {
+                if (P.handoff_threshold > 0) atomicSub(P.live, n);
+                atomicSub(P.promo_live, n);
+            }
+            idle = 0;
+        } else {
+            int alive = 0, popped = 0, pushed = 0;
+            if (lane == 0) {
+                alive = __hip_atomic_load(P.producers_alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                popped = __hip_atomic_load(P.promo_pop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pushed = __hip_atomic_load(P.promo_push, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            alive = __shfl(alive, 0);
+            popped = __shfl(popped, 0);
+            pushed = __shfl(pushed, 0);
+            if (alive == 0 && popped >= pushed) break;
+            if (++idle > (1 << 24)) {
+                if (lane == 0) atomicAdd(P.promo_err, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+}
+
 // Starting state of every launch ray (one thread per ray).
 template <typename T>
 __device__ __forceinline__ void start_body(const TraceParams<T> &P)
@@ -579,6 +777,7 @@ __device__ __forceinline__ void start_body(const TraceParams<T> &P)
     RayRec &rec = P.rec[ray];
     rec.L = L;
     rec.status = -1;
+    if (P.promo_ids) P.promo_ids[ray] = -1;
 }
 
 // Outputs of every launch ray (one thread per ray), after the trace kernels,
@@ -654,13 +853,15 @@ __global__ __launch_bounds__(64) void k_ionogram(const double *__restrict__ elev
 template <typename T, int IP>
 __global__ __launch_bounds__(64) void k_trace(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
 {
-    trace_body<T, IP>(P, Pp);
+    if (int(blockIdx.x) >= P.n_producers) promote_body<T, IP>(P, Pp);
+    else trace_body<T, IP>(P, Pp);
 }
 template <typename T, int IP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 void k_trace_w2(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
 {
-    trace_body<T, IP>(P, Pp);
+    if (int(blockIdx.x) >= P.n_producers) promote_body<T, IP>(P, Pp);
+    else trace_body<T, IP>(P, Pp);
 }
 template <typename T, int IP>
 __global__ __launch_bounds__(64) void k_tail(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)

@@ -267,6 +267,29 @@ def test_tail_kernel_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
     assert one["total_steps"] == tail["total_steps"] == mid["total_steps"] == inwave["total_steps"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_promotion_is_bit_identical(rt, ctx, precision):
+    """Promotion waves take trapped and old rays over while the one-lane
+    waves run; outputs are identical with promotion off, on with the default
+    age, on with a small age (many rays promoted, the queue kept full), and
+    on with the tail kernel off (promoted rays run to the end)."""
+    wl = synth.ionogram_workload(0)
+    grid = rt.Grid(ctx, wl.grid)
+    try:
+        runs = [host(gpu_trace(rt, ctx, grid, wl, precision=precision, device_results=True,
+                               **kw))
+                for kw in (dict(promote_waves=-1), dict(promote_waves=16),
+                           dict(promote_waves=8, promote_age=200),
+                           dict(promote_waves=4, promote_age=-1, tail_threshold=-1))]
+    finally:
+        grid.close()
+    for k in ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "land_lat_deg",
+              "land_lon_deg", "status", "n_steps"):
+        for other in runs[1:]:
+            assert np.array_equal(runs[0][k], other[k], equal_nan=True), k
+    assert len({r["total_steps"] for r in runs}) == 1
+
+
 def test_single_ray_is_handed_off(rt, ctx, aniso_wl, aniso_grid):
     """A lone ray with the hand-off on runs in the tail kernel (at most
     `threshold` live rays) and still equals the one-lane result."""
