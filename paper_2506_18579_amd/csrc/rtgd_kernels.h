@@ -712,8 +712,11 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             head = __shfl(head, 0);
             closing = head >= P.n_rays && live <= P.handoff_threshold;
         }
-        // idle rows claim promoted rays
-        if (__ballot(ray < 0) != 0ull) {
+        // idle rows claim promoted rays: every iteration while the whole
+        // wave is idle, every eighth while another row runs (a claim costs
+        // memory round trips that would stall that row's step)
+        const unsigned long long busy = __ballot(ray >= 0);
+        if (__ballot(ray < 0) != 0ull && (busy == 0ull || (iter & 7) == 0)) {
             int r = -1;
             if (lead && ray < 0) r = claim_promoted(P);
             r = __shfl(r, lead_lane);

@@ -23,6 +23,9 @@ def main():
                     "workload's grid and transmitter, replicated")
     ap.add_argument("--tail", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
+    ap.add_argument("--ray-order", type=int, default=0)
+    ap.add_argument("--promote-waves", type=int, default=0)
+    ap.add_argument("--promote-age", type=int, default=0)
     a = ap.parse_args()
     import torch
     from paper_2506_18579_amd import rtgd, synth
@@ -47,7 +50,8 @@ def main():
     for i in range(a.reps):
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
                          exit_h_km=wl.exit_km, precision=a.precision, device_results=True, out=out,
-                         tail_threshold=a.tail, waves_per_simd=a.waves_per_simd)
+                         tail_threshold=a.tail, waves_per_simd=a.waves_per_simd, ray_order=a.ray_order,
+                         promote_waves=a.promote_waves, promote_age=a.promote_age)
         print(json.dumps({"rep": i, "workload": wl.name, "precision": a.precision,
                           "ray_steps": out["total_steps"], "kernel_ms": out["kernel_ms"]}),
               flush=True)

@@ -228,6 +228,11 @@ def test_invalid_arguments(rt, ctx, iso_wl, iso_grid, aniso_wl, aniso_grid):
     with pytest.raises(rt.RTError) as e:
         gpu_trace(rt, ctx, iso_grid, iso_wl, high_tx)
     assert e.value.code == rt.RT_E_UNSUPPORTED
+    for kw in (dict(promote_waves=65), dict(promote_waves=-2), dict(promote_age=-2),
+               dict(ray_order=3), dict(waves_per_simd=3), dict(tail_threshold=-3)):
+        with pytest.raises(rt.RTError) as e:
+            gpu_trace(rt, ctx, iso_grid, iso_wl, **kw)
+        assert e.value.code == rt.RT_E_INVALID, kw
     # the context stays usable after errors
     ok = gpu_trace(rt, ctx, iso_grid, iso_wl)
     assert ok["status"].size == 90
