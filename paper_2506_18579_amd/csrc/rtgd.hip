@@ -346,7 +346,9 @@ constexpr int kDefaultPromoteAge = 1500;
 // step counter per segment).
 struct Counters {
     int32_t head, trunc, live, n_handoff;
-    int32_t promo_push, promo_pop, promo_live, producers_alive, promo_err, pad;
+    int32_t pad0[28];          // the promotion counters on cache lines of their own
+    int32_t promo_push, promo_pop, promo_live, producers_alive, promo_err;
+    int32_t pad1[27];
 };
 
 // Workspace layout of a launch, the same on the device and in host staging

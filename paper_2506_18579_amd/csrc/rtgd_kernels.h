@@ -470,9 +470,9 @@ __device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, L
     ray = src < 0 ? -1 : r;
 }
 
-// Promotion, producer side (a one-lane wave): lanes whose ray is trapped
-// in a duct, or at least promote_age steps old, move the ray to the
-// promotion queue while there is room: trapped rays may fill all
+// Promotion, producer side (a one-lane wave, every 32nd iteration): lanes
+// whose ray is trapped in a duct, or at least promote_age steps old, move
+// the ray to the promotion queue while there is room: trapped rays may fill all
 // promote_cap places, old rays three quarters of them, so that trapped
 // rays (the longest) always find room.  The state goes to the ray's
 // record, a ticket is taken, and the ray index is published under the
@@ -610,7 +610,8 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
                 break;
             }
         }
-        if (P.promote_cap > 0 && (iter & 7) == 0) promote(P, ray, L, lane);
+        // every 32nd iteration: an attempt costs atomics on shared counters
+        if (P.promote_cap > 0 && (iter & 31) == 0) promote(P, ray, L, lane);
         int st = -1;
         if (ray >= 0) {
             st = advance<T, IP, 1>(P, Pp, ray, L, true, sc);
@@ -760,11 +761,11 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             popped = __shfl(popped, 0);
             pushed = __shfl(pushed, 0);
             if (alive == 0 && popped >= pushed) break;
-            if (++idle > (1 << 24)) {
+            if (++idle > (1 << 22)) {
                 if (lane == 0) atomicAdd(P.promo_err, 1);
                 break;
             }
-            __builtin_amdgcn_s_sleep(8);
+            __builtin_amdgcn_s_sleep(32);
         }
     }
 }
