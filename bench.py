@@ -35,15 +35,15 @@ PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (256 CU x 2.4 GHz x 128)
 PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 
 # HBM bytes of one FP64 ionogram launch (k_start, k_trace, k_tail and
-# k_finish; 16 promotion waves for trapped rays, as the autotuner picks) from
-# rocprofv3: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 1 GiB
-# device copy in the same runs).  Valid only for the device
-# sources (per-step arithmetic and trace kernels) with these hashes;
-# otherwise reported as null.
-TRAFFIC_BYTES = (74224 + 47694) * 1024
+# k_finish; the autotuned setting: hand-off at 4096 rays, 32 promotion waves
+# for trapped and grazing rays) from rocprofv3: FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000 (factors from a 1 GiB device copy in the same runs).
+# Valid only for the device sources (per-step arithmetic and trace kernels)
+# with these hashes; otherwise reported as null.
+TRAFFIC_BYTES = (76508 + 47998) * 1024
 TRAFFIC_SOURCES = {
     "rtgd_device.h": "fc2671d864d65019d61ee6dcdc3f5df412c22267d5495bb45054fd1589ddab48",
-    "rtgd_kernels.h": "1e11f67dbe5b90deaafb2559b6e520b4f96af15f6773f1c1af8754a5a06b6d49",
+    "rtgd_kernels.h": "fb270b939535acaf43f8d3a55b8b490488f224098de2db055910361bf0cf3f17",
 }
 
 

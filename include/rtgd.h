@@ -137,12 +137,17 @@ typedef struct {
                                waves run rays 16 lanes each beside the
                                one-lane waves, taking over rays trapped in a
                                duct (wave normal turning upward inside the
-                               ionosphere: they run to max_group_km) and rays
-                               older than promote_age steps; 0 = default
-                               (none), -1 = none, at most 64; ignored with
-                               tail_threshold = -2                         */
+                               ionosphere: they run to max_group_km), rays
+                               that grazed a layer peak on their first ascent
+                               (n_r falling to a positive local minimum below
+                               0.02 |n|: such rays are often trapped later)
+                               and rays older than promote_age steps;
+                               0 = default (16 for launches of at least
+                               8192 rays, else none), -1 = none, at most 64;
+                               ignored with tail_threshold = -2            */
     int32_t promote_age;    /* steps after which any ray may be promoted;
-                               0 = default (1500), -1 = trapped rays only  */
+                               0 = default and -1: never (trapped and
+                               grazing rays only)                          */
 } rt_trace_opts;
 
 /* Per-ray outputs, arrays of N_r = rt_fan_count() elements, owned by the
@@ -313,11 +318,12 @@ void rt_plan_destroy(rt_plan *plan);
  * (see rt_trace_opts).  rt_autotune traces the given fan for every
  * candidate setting (tail_threshold in {-2, -1, 8 and 16 rays per CU} x
  * waves_per_simd in {1, 2} x ray_order in {index, strided}; then, on top of
- * the fastest of those unless it is the in-wave switch, (promote_waves,
- * promote_age) in {(16, trapped rays only), (16, 3000), (32, 3000)}; one
- * untimed run, then the median device time of three), keeps the fastest if
- * it beats the library defaults by at least 2 % (else the defaults, all
- * five fields 0) and writes base with those five fields replaced to *tuned.  Choices are cached in the process under a key made of the
+ * the fastest of those unless it is the in-wave switch, promote_waves in
+ * {16, 32, 64} with promote_age -1; the first stage runs without
+ * promotion; one untimed run, then the median device time of three), keeps
+ * the fastest if it beats the library defaults by at least 2 % (else the
+ * defaults, all five fields 0) and writes base with those five fields
+ * replaced to *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on
  * or off and the ray count rounded to a power of two; a cached key is
  * answered without tracing.  Results of the trial traces are discarded

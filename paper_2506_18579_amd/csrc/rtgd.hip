@@ -326,7 +326,7 @@ struct TraceJob {
     int64_t perm = 1;          // visiting stride
     int occ = 1;               // register budget variant
     int promote = 0;           // promotion waves (0: none)
-    int promote_age = 0;       // promote rays of at least this many steps too (0: trapped rays only)
+    int promote_age = 0;       // promote rays of at least this many steps too (0: trapped and grazing rays only)
     int32_t *tcount = nullptr;
     double *traj = nullptr;
     int64_t per_ray = 0;
@@ -336,11 +336,12 @@ static_assert(sizeof(TraceParams<float>) <= sizeof(TraceParams<double>),
               "the workspace reserves room for the FP64 parameter block");
 
 // Promotion waves (rt_trace_opts::promote_waves): at most, and the library
-// defaults (0: none; promote rays of at least 1500 steps besides trapped
-// ones).
+// defaults: 16 waves for launches of at least 8192 rays (smaller ones keep
+// every wave for one-lane work), promoting trapped and grazing rays only.
 constexpr int kMaxPromoteWaves = 64;
-constexpr int kDefaultPromoteWaves = 0;
-constexpr int kDefaultPromoteAge = 1500;
+constexpr int kDefaultPromoteWaves = 16;
+constexpr int kDefaultPromoteMinRays = 8192;
+constexpr int kDefaultPromoteAge = 0;
 
 // Counters the kernels update, read back after a launch (followed by one
 // step counter per segment).
@@ -457,7 +458,8 @@ void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
     job.tail = tail > 0 ? int(std::min<int64_t>(tail, n64)) : 0;
     job.perm = opts.ray_order == 2 ? visit_stride(n64) : 1;
     // promotion runs beside the one-lane waves; not with the in-wave switch
-    const int pw = opts.promote_waves == 0 ? kDefaultPromoteWaves : opts.promote_waves;
+    const int pw = opts.promote_waves != 0 ? opts.promote_waves
+                 : (n64 >= kDefaultPromoteMinRays ? kDefaultPromoteWaves : 0);
     job.promote = (pw > 0 && !job.inwave) ? pw : 0;
     job.promote_age = opts.promote_age == 0 ? kDefaultPromoteAge : std::max(0, opts.promote_age);
     job.per_ray = opts.traj_stride > 0 && n64 > 0 ? opts.traj_capacity / n64 : 0;
@@ -1398,6 +1400,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     o.promote_waves = 0;
     o.promote_age = 0;
     st = time_opts(o, inf.default_ms);
+    o.promote_waves = -1;     // the first stage runs without promotion
     for (int oc : occs) {
         for (int tl : tails) {
             for (int od : orders) {
@@ -1408,12 +1411,12 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
                 double ms = 0;
                 st = time_opts(o, ms);
                 ++inf.n_candidates;
-                if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od, 0, 0}; }
+                if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od, -1, 0}; }
             }
         }
     }
     // then promotion on top of the best of those (not with the in-wave switch)
-    const int promos[3][2] = {{16, -1}, {16, 3000}, {32, 3000}};
+    const int promos[3][2] = {{16, -1}, {32, -1}, {64, -1}};
     if (bv.tail_threshold != -2) {
         for (const auto &pr : promos) {
             if (st != RT_OK) break;

@@ -78,7 +78,7 @@ struct TraceParams {
     // sixteen lanes each while the other waves still run one lane per ray
     int32_t n_producers;       // one-lane waves (all waves when promotion is off)
     int32_t promote_cap;       // promoted rays running or queued at most (4 per promotion wave; 0: off)
-    int32_t promote_age;       // also promote rays of at least this many steps (0: trapped rays only)
+    int32_t promote_age;       // also promote rays of at least this many steps (0: trapped and grazing rays only)
     int32_t *promo_push;       // tickets issued (promoted rays)
     int32_t *promo_pop;        // tickets claimed by promotion waves
     int32_t *promo_live;       // promoted rays not yet finished or handed off
@@ -156,8 +156,10 @@ struct Lane {
     int32_t ntraj;
     int32_t seg;          // segment of the ray
     int32_t local;        // ray index within the segment
-    int32_t trapped;      // turned upward inside the ionosphere (a duct)
-    int32_t pad;
+    int32_t trapped;      // 1: turned upward inside the ionosphere (a duct);
+                          // 2: grazed a layer peak on the first ascent
+    float nr_lo;          // smallest n_r so far on the first ascent (one-lane
+                          // kernels, promotion on); negative once it ended
 };
 
 // Per launch ray, in device memory: the starting state, written by k_start
@@ -242,7 +244,7 @@ __device__ __forceinline__ void init_ray(const TraceParams<T> &P, int ray, Lane 
     L.steps = 0;
     L.ntraj = 0;
     L.trapped = 0;
-    L.pad = 0;
+    L.nr_lo = 3.0e38f;
     if (P.traj_stride > 0 && write) put_traj(P, ray, L);
 }
 
@@ -348,6 +350,10 @@ __device__ __attribute__((noinline)) Lane graze_back(const TraceParams<T> *Pp, i
     return L;
 }
 
+// n_r / |n| below which a turning point passed on the first ascent counts
+// as grazing (for promotion only).
+constexpr double kGrazeQ = 0.02;
+
 // One RK4 step plus the termination tests.  Returns the ray status, or -1
 // if the ray goes on.  `write` is false on the lanes of a row that only
 // shadow the row's leader (no memory writes).  P is the caller's copy of
@@ -366,6 +372,24 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParam
     // grid bottom is trapped between layers: such rays run to the maximum
     // group path (used to pick rays for promotion only)
     if (nr0 < 0.0 && L.y[3] >= 0.0 && h > P.floor_h + 5.0) L.trapped = 1;
+    // a ray whose n_r, on its first ascent, falls to a positive local minimum
+    // below kGrazeQ |n| and then grows again has crossed a layer peak at
+    // grazing incidence: on the way down such rays are often turned back up
+    // by the same layer (trapped above it) or run far along a layer, and they
+    // are recognised here hundreds of steps before their first upward turn
+    if constexpr (LANES == 1) {
+        if (P.promote_cap > 0 && L.nr_lo >= 0.0f) {
+            const double nr = L.y[3], lo = double(L.nr_lo);
+            if (nr < 0.0) {
+                L.nr_lo = -1.0f;
+            } else if (nr < lo) {
+                L.nr_lo = float(nr);
+            } else if (nr > lo && lo * lo < kGrazeQ * kGrazeQ * fm(nr, nr, fm(L.y[4], L.y[4], L.y[5] * L.y[5]))) {
+                if (L.trapped == 0) L.trapped = 2;
+                L.nr_lo = -1.0f;
+            }
+        }
+    }
     int status = -1;
     bool finite = ok;
 #pragma unroll
@@ -464,17 +488,18 @@ __device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, L
     M.seg = __shfl(L.seg, s);
     M.local = __shfl(L.local, s);
     M.trapped = __shfl(L.trapped, s);
-    M.pad = 0;
+    M.nr_lo = -1.0f;
     const int r = __shfl(ray, s);
     L = M;
     ray = src < 0 ? -1 : r;
 }
 
 // Promotion, producer side (a one-lane wave, every 32nd iteration): lanes
-// whose ray is trapped in a duct, or at least promote_age steps old, move
-// the ray to the promotion queue while there is room: trapped rays may fill all
-// promote_cap places, old rays three quarters of them, so that trapped
-// rays (the longest) always find room.  The state goes to the ray's
+// whose ray is trapped in a duct or grazed a layer peak (see advance), or is
+// at least promote_age steps old, move the ray to the promotion queue while
+// there is room: trapped and grazing rays may fill all promote_cap places,
+// old rays three quarters of them, so that the former (the longest rays)
+// always find room.  The state goes to the ray's
 // record, a ticket is taken, and the ray index is published under the
 // ticket (release).  The lane then idles and refills from the launch queue.
 template <typename T>

@@ -274,16 +274,17 @@ def test_tail_kernel_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_promotion_is_bit_identical(rt, ctx, precision):
-    """Promotion waves take trapped and old rays over while the one-lane
-    waves run; outputs are identical with promotion off, on with the default
-    age, on with a small age (many rays promoted, the queue kept full), and
-    on with the tail kernel off (promoted rays run to the end)."""
+    """Promotion waves take trapped, grazing and old rays over while the
+    one-lane waves run; outputs are identical with promotion off, at the
+    default (16 waves for this fan, trapped and grazing rays), with the most
+    waves, with a small age (many rays promoted, the queue kept full), and
+    with the tail kernel off (promoted rays run to the end)."""
     wl = synth.ionogram_workload(0)
     grid = rt.Grid(ctx, wl.grid)
     try:
         runs = [host(gpu_trace(rt, ctx, grid, wl, precision=precision, device_results=True,
                                **kw))
-                for kw in (dict(promote_waves=-1), dict(promote_waves=16),
+                for kw in (dict(promote_waves=-1), dict(), dict(promote_waves=64),
                            dict(promote_waves=8, promote_age=200),
                            dict(promote_waves=4, promote_age=-1, tail_threshold=-1))]
     finally:
