@@ -144,7 +144,13 @@ typedef struct {
                                and rays older than promote_age steps;
                                0 = default (16 for launches of at least
                                8192 rays, else none), -1 = none, at most 64;
-                               ignored with tail_threshold = -2            */
+                               ignored with tail_threshold = -2.  An idle
+                               promotion wave waits for work at most a
+                               wall-clock bound far above the launch's
+                               one-lane phase (at least 10 s; the variable
+                               RTGD_PROMOTE_IDLE_MS overrides it, for
+                               tests); a wait that runs out fails the call
+                               with RT_E_DEVICE                            */
     int32_t promote_age;    /* steps after which any ray may be promoted;
                                0 = default and -1: never (trapped and
                                grazing rays only)                          */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstddef>
 #include <deque>
 #include <map>
@@ -31,6 +32,7 @@ struct rt_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int n_cu = 0;
+    int64_t wall_khz = 0;       // rate of the device's constant wall clock
     // workspace (grow-only)
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -180,6 +182,10 @@ rt_status rt_ctx_create(int32_t device, void *stream, rt_ctx **out)
         return RT_E_DEVICE;
     }
     c->n_cu = prop.multiProcessorCount;
+    int wall = 0;
+    if (hipDeviceGetAttribute(&wall, hipDeviceAttributeWallClockRate, device) != hipSuccess || wall <= 0)
+        wall = 100000;          // 100 MHz, the usual rate
+    c->wall_khz = wall;
     *out = c;
     return RT_OK;
 }
@@ -484,7 +490,7 @@ bool compatible(const JobSeg &a, const rt_trace_opts &oa, const JobSeg &b, const
 
 template <typename T>
 void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char *dev, int n_producers,
-                 int n_promote)
+                 int n_promote, int64_t wall_khz)
 {
     const JobSeg &s0 = job.segs[0];
     const rt_grid_geom &gq = s0.grid->geom;
@@ -527,6 +533,18 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.producers_alive = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, producers_alive));
     P.promo_err = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_err));
     P.promo_ids = reinterpret_cast<int32_t *>(dev + lay.ids);
+    // Longest wait of an idle promotion wave while one-lane waves still run,
+    // in wall-clock ticks: far above the one-lane waves' worst case (every
+    // ray of a lane at max_steps, 50 us per step, a quarter of the waves
+    // resident at a time), and at least 10 s.  Only a fault would reach it.
+    const double lane_rays = std::ceil(double(job.n_rays) / (64.0 * std::max(1, n_producers))) + 1.0;
+    double secs = std::max(10.0, 4.0 * lane_rays * double(P.max_steps) * 50e-6);
+    // diagnostic override (milliseconds), for testing the timeout report
+    if (const char *e = std::getenv("RTGD_PROMOTE_IDLE_MS")) {
+        const double ms = std::atof(e);
+        if (ms > 0.0) secs = ms * 1e-3;
+    }
+    P.idle_ticks = int64_t(std::min(secs * double(wall_khz) * 1e3, 9.0e18));
     P.handoff_threshold = job.tail;
     P.inwave = job.inwave;
     P.perm_stride = job.perm;
@@ -615,11 +633,11 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     TraceParams<double> Pd{};
     void *pargs;
     if (mixed) {
-        fill_params<float>(job, lay, Pf, dev, producers, n_promote);
+        fill_params<float>(job, lay, Pf, dev, producers, n_promote, ctx->wall_khz);
         std::memcpy(host + lay.par, &Pf, sizeof(Pf));
         pargs = &Pf;
     } else {
-        fill_params<double>(job, lay, Pd, dev, producers, n_promote);
+        fill_params<double>(job, lay, Pd, dev, producers, n_promote, ctx->wall_khz);
         std::memcpy(host + lay.par, &Pd, sizeof(Pd));
         pargs = &Pd;
     }

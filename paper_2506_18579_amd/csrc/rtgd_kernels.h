@@ -83,7 +83,8 @@ struct TraceParams {
     int32_t *promo_pop;        // tickets claimed by promotion waves
     int32_t *promo_live;       // promoted rays not yet finished or handed off
     int32_t *producers_alive;  // one-lane waves still running
-    int32_t *promo_err;        // claims that timed out (reported as a launch error)
+    int32_t *promo_err;        // waits that timed out (reported as a launch error)
+    int64_t idle_ticks;        // wall-clock bound of an idle promotion wave's wait
     int32_t *promo_ids;        // ray of each ticket, -1 until published (n_rays entries)
 };
 
@@ -712,7 +713,8 @@ __device__ __forceinline__ int handoff_rows(bool pred, int ray, const Lane &L, i
 // after that, go to the tail kernel instead.  The wave exits once no
 // one-lane wave is left and every ticket is claimed (one-lane waves always
 // finish, so this is reached); an idle wait with work still possible is
-// bounded and counted in promo_err if it runs out.
+// bounded in wall-clock time (idle_ticks, far above any launch's one-lane
+// phase) and counted in promo_err if it runs out.
 template <typename T, int IP>
 __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const TraceParams<T> *Pp)
 {
@@ -726,7 +728,8 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
     int ray = -1;
     Lane L;
     bool closing = false;
-    int idle = 0;
+    bool idling = false;
+    long long idle_t0 = 0;
     for (int iter = 0;; ++iter) {
         if (!closing && P.handoff_threshold > 0 && (iter & 7) == 0) {
             int live = 0, head = 0;
@@ -774,7 +777,7 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
                 if (P.handoff_threshold > 0) atomicSub(P.live, n);
                 atomicSub(P.promo_live, n);
             }
-            idle = 0;
+            idling = false;
         } else {
             int alive = 0, popped = 0, pushed = 0;
             if (lane == 0) {
@@ -786,7 +789,11 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             popped = __shfl(popped, 0);
             pushed = __shfl(pushed, 0);
             if (alive == 0 && popped >= pushed) break;
-            if (++idle > (1 << 22)) {
+            const long long now = wall_clock64();
+            if (!idling) {
+                idling = true;
+                idle_t0 = now;
+            } else if (now - idle_t0 > P.idle_ticks) {
                 if (lane == 0) atomicAdd(P.promo_err, 1);
                 break;
             }

@@ -238,6 +238,22 @@ def test_invalid_arguments(rt, ctx, iso_wl, iso_grid, aniso_wl, aniso_grid):
     assert ok["status"].size == 90
 
 
+def test_promotion_timeout_is_reported(rt, ctx, aniso_wl, aniso_grid, monkeypatch):
+    """An idle promotion wave's wait is bounded in wall-clock time.  With the
+    bound forced down to a microsecond from the host, the promotion waves give
+    up at once: the launch reports a device error instead of hanging, and the
+    context stays usable."""
+    monkeypatch.setenv("RTGD_PROMOTE_IDLE_MS", "0.001")
+    with pytest.raises(rt.RTError) as e:
+        gpu_trace(rt, ctx, aniso_grid, aniso_wl, promote_waves=16, promote_age=-1)
+    assert e.value.code == rt.RT_E_DEVICE
+    monkeypatch.delenv("RTGD_PROMOTE_IDLE_MS")
+    a = gpu_trace(rt, ctx, aniso_grid, aniso_wl, promote_waves=16, promote_age=-1)
+    b = gpu_trace(rt, ctx, aniso_grid, aniso_wl, promote_waves=-1)
+    for k in ("group_km", "range_km", "status", "n_steps"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
 def test_grid_create_rejects_bad_values(rt, ctx):
     geom = synth.GridGeom(6, 6, 8, 28.0, 0.5, 108.0, 0.5, 100.0, 3.0)
     vals = np.ones((6, 6, 8)) * 1e11
