@@ -731,7 +731,13 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
     bool idling = false;
     long long idle_t0 = 0;
     for (int iter = 0;; ++iter) {
-        if (!closing && P.handoff_threshold > 0 && (iter & 7) == 0) {
+        // The shared counters are polled every iteration while the whole wave
+        // is idle, and every 32nd while a row runs: a poll is a memory round
+        // trip, and the running rows (the longest rays of the launch) stall
+        // for it.
+        const unsigned long long busy = __ballot(ray >= 0);
+        const bool poll = busy == 0ull || (iter & 31) == 0;
+        if (!closing && P.handoff_threshold > 0 && poll) {
             int live = 0, head = 0;
             if (lane == 0) {
                 live = __hip_atomic_load(P.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -741,11 +747,8 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             head = __shfl(head, 0);
             closing = head >= P.n_rays && live <= P.handoff_threshold;
         }
-        // idle rows claim promoted rays: every iteration while the whole
-        // wave is idle, every eighth while another row runs (a claim costs
-        // memory round trips that would stall that row's step)
-        const unsigned long long busy = __ballot(ray >= 0);
-        if (__ballot(ray < 0) != 0ull && (busy == 0ull || (iter & 7) == 0)) {
+        // idle rows claim promoted rays
+        if (poll && __ballot(ray < 0) != 0ull) {
             int r = -1;
             if (lead && ray < 0) r = claim_promoted(P);
             r = __shfl(r, lead_lane);
