@@ -40,10 +40,10 @@ PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 # WRITE_SIZE x 1.000 (factors from a 1 GiB device copy in the same runs).
 # Valid only for the device sources (per-step arithmetic and trace kernels)
 # with these hashes; otherwise reported as null.
-TRAFFIC_BYTES = (76508 + 47998) * 1024
+TRAFFIC_BYTES = (76280 + 48017) * 1024
 TRAFFIC_SOURCES = {
     "rtgd_device.h": "fc2671d864d65019d61ee6dcdc3f5df412c22267d5495bb45054fd1589ddab48",
-    "rtgd_kernels.h": "fb270b939535acaf43f8d3a55b8b490488f224098de2db055910361bf0cf3f17",
+    "rtgd_kernels.h": "3700c5caf5f3c2d5f2c992a4bc176ea4ea361702d9c0259e38cdf231dc9335a1",
 }
 
 
@@ -124,8 +124,15 @@ def main():
     e2e_ms = float(np.median([x[0] for x in e2e])) * 1e3
     fan_wl = synth.aniso_fan_workload(0)
     fan_grid = rtgd.Grid(ctx, fan_wl.grid)
-    fan64 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "fp64", max(3, a.steps), 1)
-    fan32 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "mixed", max(3, a.steps), 1)
+    # fan latency: 20 launches each, with the library defaults and with the
+    # settings the autotuner picks for this fan
+    fan64 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "fp64", 20, 2)
+    fan32 = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "mixed", 20, 2)
+    fkw = dict(step_km=fan_wl.step_km, max_group_km=fan_wl.max_group_km, exit_h_km=fan_wl.exit_km)
+    ftune64 = rtgd.autotune(ctx, fan_grid, fan_wl.fan, precision="fp64", **fkw)
+    ftune32 = rtgd.autotune(ctx, fan_grid, fan_wl.fan, precision="mixed", **fkw)
+    fan64t = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "fp64", 20, 2, ftune64)
+    fan32t = time_trace(rtgd, torch, ctx, fan_grid, fan_wl, "mixed", 20, 2, ftune32)
     fan_grid.close()
 
     serving = {}
@@ -258,6 +265,8 @@ def main():
 
     lat = np.array(fan64["walls"]) * 1e3
     lat32 = np.array(fan32["walls"]) * 1e3
+    latt = np.array(fan64t["walls"]) * 1e3
+    latt32 = np.array(fan32t["walls"]) * 1e3
     line = {
         "metric": "ray-steps/s at stated accuracy, FP64 vs mixed; p50/p99 ray-fan latency",
         "value": value,
@@ -297,7 +306,15 @@ def main():
             "fp64_latency_ms_p50": float(np.percentile(lat, 50)),
             "fp64_latency_ms_p99": float(np.percentile(lat, 99)),
             "mixed_latency_ms_p50": float(np.percentile(lat32, 50)),
-            "mixed_latency_ms_p99": float(np.percentile(lat32, 99))},
+            "mixed_latency_ms_p99": float(np.percentile(lat32, 99)),
+            "tuned_fp64_latency_ms_p50": float(np.percentile(latt, 50)),
+            "tuned_fp64_latency_ms_p99": float(np.percentile(latt, 99)),
+            "tuned_mixed_latency_ms_p50": float(np.percentile(latt32, 50)),
+            "tuned_mixed_latency_ms_p99": float(np.percentile(latt32, 99)),
+            "tuning": {"fp64": {k: ftune64[k] for k in TUNED_KNOBS},
+                       "mixed": {k: ftune32[k] for k in TUNED_KNOBS}},
+            "note": "wall time of one rt_trace call (device results), 20 calls each; "
+                    "library defaults, then the autotuned settings for this fan"},
         "serving": dict(serving, workload=f"{a.serve_requests} requests, 90 % ray fans of "
                         "1-20,000 rays (log-uniform) and 10 % ionogram syntheses (500-4,000-ray "
                         "sweeps of the 1200 km link), 4 resident 181x181x226 snapshots, 4 slots, "

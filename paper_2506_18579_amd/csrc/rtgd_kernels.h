@@ -66,7 +66,7 @@ struct TraceParams {
     // scheduling
     int32_t *queue_head;
     int32_t *truncated;
-    // hand-off of the last live rays to the 4-lanes-per-ray tail kernel
+    // hand-off of the last live rays to the 16-lanes-per-ray tail kernel
     int32_t *live;             // rays neither finished nor handed off
     int32_t *n_handoff;        // records written
     struct Handoff *handoff;   // capacity handoff_threshold
