@@ -5,6 +5,13 @@
  * Each function states the passage of the paper it follows.  No blocking,
  * fusion or reordering beyond what the definitions state.  Rays are
  * independent; OpenMP only distributes whole rays over threads.
+ *
+ * Pins (tests/test_oracle_*.py, tests/test_ionogram.py): every function is
+ * checked against closed forms, high-precision quadrature, invariants or
+ * finite differences.  Anisotropic whole rays have no closed form and the
+ * paper prints no worked example for them: they are pinned by invariants
+ * only (H = 0 along the ray, O = X as the field vanishes, the partials
+ * against finite differences of H).
  */
 #include "rtgd_oracle.h"
 

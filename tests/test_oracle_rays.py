@@ -189,6 +189,46 @@ def test_bouguer_invariant_along_ray(orc, tx, az):
     assert abs(r["az_dev_deg"][0]) < 1e-9
 
 
+@pytest.mark.parametrize("f,elev", [(6.0, 1.0), (6.0, 6.5), (8.0, 4.0)])
+def test_grazing_return_follows_the_vacuum_chord(orc, f, elev):
+    """Reading of the landing rule for a line that misses the Earth (Sec. II-C
+    termination): from a transmitter at 50 km, a ray launched below about 7 deg
+    comes back down below the 60 km floor on a straight vacuum line whose
+    perigee r0 cos(beta0) lies above the ground, so it passes under the
+    layer and climbs back to the floor, hop after hop, until the maximum
+    group path.  Pins, from the geometry of a straight line in a sphere:
+    * the chord from the recorded point (r1, direction n) to the floor is
+      sqrt(r1^2 - p^2) + sqrt(rb^2 - p^2) with perigee p = r1 |n_t| / |n|; both
+      the group and the phase path grow by it (plus the next 1 km step,
+      in vacuum);
+    * the Bouguer invariant r |n_t| holds through every chord;
+    * in this spherically symmetric medium every hop repeats: equal group
+      path and equal colatitude advance per hop."""
+    med = orc.OracleMedium.chapman(8.0, 300.0, 50.0, floor_km=60.0)
+    rb = R + 60.0
+    r = orc.trace(med, [elev], 0.0, f, [1], B0=0.0, tx=(30.0, 110.0, 50.0), step=1.0,
+                  max_group=8000.0, exit_h=500.0, traj_stride=1, traj_per_ray=9000)
+    n = r["traj_count"][0]
+    tr = r["traj"][0, :n]
+    assert int(r["status"][0]) == 2
+    inv = tr[:, 0] * np.sqrt(tr[:, 4] ** 2 + tr[:, 5] ** 2)
+    expect = (R + 50.0) * math.cos(math.radians(elev))
+    assert np.abs(inv / expect - 1.0).max() < 1e-10
+    chords = np.flatnonzero((tr[:, 0] - R < 60.0) & (tr[:, 3] < 0.0))
+    assert chords.size >= 2 and chords[-1] + 1 < n
+    for k in chords:
+        nn = math.sqrt(float((tr[k, 3:6] ** 2).sum()))
+        p = tr[k, 0] * math.sqrt(tr[k, 4] ** 2 + tr[k, 5] ** 2) / nn
+        assert p > R
+        chord = math.sqrt(tr[k, 0] ** 2 - p * p) + math.sqrt(rb * rb - p * p)
+        assert abs(tr[k + 1, 7] - tr[k, 7] - 1.0 - chord) < 1e-8
+        assert abs(tr[k + 1, 6] - tr[k, 6] - 1.0 - chord) < 1e-8
+    hop_p = np.diff(tr[chords, 7])
+    hop_th = np.diff(tr[chords, 1])
+    assert np.abs(hop_p / hop_p[0] - 1.0).max() < 1e-9
+    assert np.abs(hop_th / hop_th[0] - 1.0).max() < 1e-9
+
+
 def test_azimuthal_symmetry(orc):
     """In a spherically symmetric medium the launch azimuth changes nothing
     but the direction: same range, group path, zero azimuth deviation."""

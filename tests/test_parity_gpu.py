@@ -5,6 +5,8 @@ and a ragged tail; sampled parity at the full workload sizes in the launch
 configuration the benchmark uses; edge cases (empty fan, grid edges, maximum
 path, invalid arguments, trajectories, determinism, batch independence).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -64,6 +66,34 @@ def test_iso_chapman_every_ray(rt, ctx, orc, iso_wl, iso_grid):
     print("iso worst rel err", rep["worst_rel"], "ill-conditioned", rep["ill_conditioned"])
     # 1..51 deg return to ground, 52..90 escape (10 MHz through foF2 = 8 MHz)
     assert np.all(g["status"][:51] == 0) and np.all(g["status"][51:] == 1)
+
+
+def test_grazing_returns_match_oracle(rt, ctx, orc, iso_wl, iso_grid):
+    """Rays from a transmitter at 50 km launched below about 7 deg come back
+    below the grid bottom on vacuum lines that miss the Earth and climb back
+    into the grid (the grazing branch of the landing rule), hop after hop, up
+    to the maximum group path.  Every ray against the oracle; the 16-lane
+    path (every ray handed to the tail kernel at once) is bit-identical.
+    The azimuths keep the hops away from the poles: a meridional ray that
+    crosses a pole reaches the antipodal meridian, where the longitude of
+    the spherical state is a tie between -180 and +180 deg from the
+    transmitter that rounding decides."""
+    fan = synth.Fan(30.0, 110.0, 50.0, np.array([1.0, 4.0, 6.5]), np.array([90.0, 135.0]),
+                    np.array([6.0, 8.0]), (1,))
+    wl = dataclasses.replace(iso_wl, max_group_km=8000.0)
+    g = gpu_trace(rt, ctx, iso_grid, wl, fan, tail_threshold=-1)
+    rays = fan.expand()
+    tr = oracle_tracer(orc, wl, fan)
+    o = tr(*rays)
+    rep = compare(g, o, rays, tr)
+    print("grazing worst rel err", rep["worst_rel"])
+    assert np.all(g["status"] == 2)
+    # chords add path without steps: fewer steps than max_group / step
+    assert np.all(g["n_steps"] < 7000)
+    t16 = gpu_trace(rt, ctx, iso_grid, wl, fan, tail_threshold=fan.n_rays)
+    for k in ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "land_lat_deg",
+              "land_lon_deg", "status", "n_steps"):
+        assert np.array_equal(g[k], t16[k], equal_nan=True), k
 
 
 def _subfan(wl):
