@@ -619,9 +619,15 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     // One-lane waves first, promotion waves after them: blocks are
     // dispatched in index order, so a promotion wave runs only once every
     // one-lane wave is resident.  All of them fit at once on an idle GPU.
+    // With promotion on, a single-request launch holds at most one wave per
+    // SIMD: a promotion wave runs the launch's longest rays, and beside a
+    // one-lane wave on the same SIMD it would issue at half rate (the FP32
+    // kernels fit two waves per SIMD).  Launches that batch several server
+    // requests keep every resident wave for throughput.
     const int max_waves = resident_waves<double>(ctx, kt);
     const int n_promote = job.promote > 0 && max_waves > 2 * job.promote ? job.promote : 0;
-    const int producers = std::max(1, std::min((job.n_rays + 63) / 64, max_waves - n_promote));
+    const int cap = n_promote > 0 && job.segs.size() == 1 ? std::min(max_waves, 4 * ctx->n_cu) : max_waves;
+    const int producers = std::max(1, std::min((job.n_rays + 63) / 64, cap - n_promote));
     const int waves = producers + n_promote;
     Counters hc{};
     hc.live = job.n_rays;
