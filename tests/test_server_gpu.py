@@ -87,6 +87,28 @@ def test_each_result_same_alone_and_in_mix(rt, ctx, grids, precision):
         same(mixed[rid], alone)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_merged_launch_matches_alone(rt, ctx, grids, precision):
+    """Three 6,000-ray requests queued behind one slot are launched together
+    (18,000 rays: enough for the default promotion waves, which a launch of
+    several requests runs beside two one-lane waves per SIMD where they fit).
+    Every result equals, bit for bit, its fan traced alone (6,000 rays: no
+    promotion)."""
+    fans = [synth.Fan(30.0, 110.0, 0.0, np.linspace(5.0, 65.0, 60), np.linspace(-60.0, 60.0, 100),
+                      np.array([f]), (m,)) for f, m in ((7.0, 1), (9.5, -1), (12.0, 1))]
+    srv = rt.Server(ctx, n_slots=1, mem_budget_bytes=64 << 20)
+    try:
+        ids = {srv.submit(grids[k % len(grids)], fan, **opts(precision)): k for k, fan in enumerate(fans)}
+        done = drain(srv, len(fans))
+        got = {rid: srv.fetch(rid, done[rid]["n_rays"]) for rid in ids}
+    finally:
+        srv.close()
+    for rid, k in ids.items():
+        alone = rt.trace(ctx, grids[k % len(grids)], fans[k], **opts(precision))
+        assert done[rid]["total_steps"] == alone["total_steps"]
+        same(got[rid], alone)
+
+
 def test_admission_by_memory(rt, ctx, grids):
     """An arena that holds one request at a time: all requests still finish,
     in submission order, with the same results."""
