@@ -93,6 +93,29 @@ def test_plan_replays_equal_eager(rt, ctx, grid, wl, precision):
         plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plan_with_promotion_replays_equal_eager(rt, ctx, grid, wl, precision):
+    """The whole 24,576-ray fan: enough rays for the default promotion waves.
+    Three replays (promotion counters and tickets re-initialised by the
+    graph each time) equal the eager trace bit for bit."""
+    kw = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km,
+              precision=precision)
+    eager = rt.trace(ctx, grid, wl.fan, **kw)
+    plan = rt.Plan(ctx, grid, wl.fan, **kw)
+    try:
+        for rep in range(3):
+            for v in plan.out.values():
+                v.fill_(-7)
+            plan.launch()
+            steps, ms = plan.wait()
+            got = host(plan.out)
+            assert steps == eager["total_steps"] and ms > 0
+            for k in KEYS:
+                assert np.array_equal(got[k], eager[k], equal_nan=True), (rep, k)
+    finally:
+        plan.close()
+
+
 def test_plan_rejects_host_results_and_empty_fans(rt, ctx, grid, wl):
     import ctypes
     fan = synth.sub_fan(wl.fan, elev_idx=[0], az_idx=[0])
