@@ -182,6 +182,21 @@ def test_trajectory_records_match_oracle(rt, ctx, orc, aniso_wl, aniso_grid):
         assert np.max(np.abs(a - b) / scale) < 1e-9
 
 
+def test_trajectories_identical_with_promotion(rt, ctx, aniso_wl, aniso_grid):
+    """The whole 24,576-ray fan with trajectories: the default promotion
+    waves (which record their rays' points themselves) give the same records
+    as a launch without promotion, and the same outputs."""
+    kw = dict(traj_stride=100, traj_per_ray=45)
+    a = gpu_trace(rt, ctx, aniso_grid, aniso_wl, **kw)
+    b = gpu_trace(rt, ctx, aniso_grid, aniso_wl, promote_waves=-1, **kw)
+    assert np.array_equal(a["traj_count"], b["traj_count"])
+    for k in ("group_km", "range_km", "status", "n_steps"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    for i in range(a["status"].size):
+        n = a["traj_count"][i]
+        assert np.array_equal(a["traj"][i, :n], b["traj"][i, :n]), i
+
+
 def test_trajectory_truncation_is_reported(rt, ctx, aniso_wl, aniso_grid):
     fan = synth.sub_fan(aniso_wl.fan, elev_idx=[5], az_idx=[10], freq_idx=[0], modes=(1,))
     g = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, traj_stride=1, traj_per_ray=10)
