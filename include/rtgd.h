@@ -144,7 +144,10 @@ typedef struct {
                                and rays older than promote_age steps;
                                0 = default (16 for launches of at least
                                8192 rays, else none), -1 = none, at most 64;
-                               ignored with tail_threshold = -2.  An idle
+                               ignored with tail_threshold = -2.  With
+                               promotion on, an rt_trace launch holds at
+                               most one wave per SIMD (so that no promotion
+                               wave shares one).  An idle
                                promotion wave waits for work at most a
                                wall-clock bound far above the launch's
                                one-lane phase (at least 10 s; the variable
