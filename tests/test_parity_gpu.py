@@ -146,6 +146,31 @@ def test_aniso_full_fan_sampled(rt, ctx, orc, aniso_wl, aniso_grid):
     print("status histogram", np.bincount(g["status"], minlength=4))
 
 
+def test_two_million_ray_fan_sampled(rt, ctx, orc, aniso_wl, aniso_grid):
+    """A fan of 2^21 = 2,097,152 rays (128 elevations x 128 azimuths x 64
+    frequencies x O/X; queue tickets, ray records and outputs at scale), 300 km
+    of group path each: the per-ray step counts add up to the launch total,
+    every status is valid, and a seeded sample of 256 rays, the first and the
+    last included, matches the oracle."""
+    fan = synth.Fan(30.0, 110.0, 0.0, np.linspace(2.0, 80.0, 128), np.linspace(-60.0, 60.0, 128),
+                    np.linspace(3.0, 25.0, 64), (1, -1))
+    wl = dataclasses.replace(aniso_wl, max_group_km=300.0)
+    n = fan.n_rays
+    assert n == 1 << 21
+    g = host(gpu_trace(rt, ctx, aniso_grid, wl, fan, device_results=True))
+    assert g["status"].size == n
+    assert np.all((g["status"] >= 0) & (g["status"] <= 3))
+    assert g["total_steps"] == int(g["n_steps"].astype(np.int64).sum())
+    rng = np.random.default_rng(21)
+    idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 254, replace=False)]))
+    e, a, f, m = fan.expand()
+    rays = (e[idx], a[idx], f[idx], m[idx])
+    tr = oracle_tracer(orc, wl, fan)
+    o = tr(*rays)
+    rep = compare(g, o, rays, tr, gpu_idx=idx)
+    print("2^21-ray fan sampled worst", rep["worst_rel"], "ill", len(rep["ill_conditioned"]))
+
+
 def test_ionogram_full_sampled(rt, ctx, orc):
     """Ionogram sweep, 112,400 rays (exit 1000 km, 8000 km max path) on the
     GPU; a seeded sample of 96 against the oracle."""
