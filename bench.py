@@ -6,9 +6,10 @@ One step = one rt_trace of the whole oblique-ionogram sweep (181x181x226
 anisotropic grid, 281 frequencies x 2 modes x 200 elevations = 112,400
 rays, FP64), grid and output buffers resident in HBM.  The same sweep is
 timed in mixed precision, the 24,576-ray anisotropic fan in both
-precisions, and fan latency percentiles are reported.  Accuracy is measured
-on a sample against the FP64 CPU oracle, which is also timed on the host
-cores as the CPU baseline.  Prints one JSON line.
+precisions, and fan latency percentiles are reported.  Every ray of the
+sweep is checked against the FP64 CPU oracle in both precisions, and the
+oracle is timed on the host cores as the CPU baseline.  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -23,14 +24,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per RK4 step (4 right-hand sides + combine),
-# counted from the method (add/mul = 1, FMA = 2, div/sqrt/sincos = 1):
-# per RHS: cell location 13, 1-D GD weights 3 x 65, 4x4x4 contraction of
-# value + 3 partials 352 (+7 scaling), dipole 16, A-H setup 15, A-H partials
-# 42, Hamiltonian partials 50, ray equations 40 -> 730 (anisotropic);
-# isotropic RHS 617.  Per step 4 RHS + 136 (RK4 stages, termination).
-FLOPS_PER_STEP_ANISO = 4 * 730 + 136
-FLOPS_PER_STEP_ISO = 4 * 617 + 136
+# Algorithmic operations per RK4 ray-step (4 right-hand sides, stage
+# combination, termination tests) by wave mode, from the oracle's counting
+# build (oracle/op_count.cpp; +, -, *, / and libm calls count 1), with the
+# GD weights in Horner form and the 4x4x4 contraction sum-factorised;
+# tests/test_oracle_op_count.py recomputes them.
+FLOPS_PER_STEP = {"O": 3346.0, "X": 3278.0, "iso": 2666.0}
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (256 CU x 2.4 GHz x 128)
 PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 
@@ -81,7 +80,7 @@ def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup, tune=None):
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
                          exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out, **kw)
     torch.cuda.synchronize()
-    walls, kms, total = [], [], 0
+    walls, kms, tms, lms, total = [], [], [], [], 0
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
@@ -89,10 +88,60 @@ def time_trace(rtgd, torch, ctx, grid, wl, precision, steps, warmup, tune=None):
                          exit_h_km=wl.exit_km, precision=precision, device_results=True, out=out, **kw)
         walls.append(time.perf_counter() - ts)
         kms.append(out["kernel_ms"])
+        tms.append(out["trace_ms"])
+        lms.append(out["tail_ms"])
         total += out["total_steps"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    return dict(out=out, elapsed=elapsed, walls=walls, kernel_ms=kms, ray_steps=total)
+    return dict(out=out, elapsed=elapsed, walls=walls, kernel_ms=kms, trace_ms=tms, tail_ms=lms,
+                ray_steps=total)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def roofline(res, modes, run, wl, precision):
+    """Algorithmic flops of one sweep (each ray's RK4 steps times the flops of
+    a step in its mode) over the launch's device time, against the VALU peak
+    that bounds the path: FP64, or for the mixed path the FP32 rate without
+    packed math, which equals the FP64 rate.  Also per kernel: the one-lane
+    kernel (with its promotion rows) and the tail kernel, from the ray-steps
+    each ran and its own device time."""
+    steps = np.asarray(res["n_steps"], dtype=np.float64)
+    if wl.grid.B0_T == 0.0:
+        per_step = np.full(steps.size, FLOPS_PER_STEP["iso"])
+    else:
+        per_step = np.where(np.asarray(modes) > 0, FLOPS_PER_STEP["O"], FLOPS_PER_STEP["X"])
+    flops = float((steps * per_step).sum())
+    avg = flops / steps.sum()
+    kms = float(np.mean(run["kernel_ms"]))
+    achieved = flops / (kms * 1e-3) / 1e12
+    peak = PEAK_FP64_VALU_TFLOPS
+    one, promo, rows = res["phase_steps"]
+    tms, lms = float(np.mean(run["trace_ms"])), float(np.mean(run["tail_ms"]))
+    per_kernel = {
+        "k_start+k_trace": {"ray_steps": one + promo, "ray_steps_one_lane": one,
+                            "ray_steps_promotion_rows": promo, "ms": tms,
+                            "frac": (one + promo) * avg / (tms * 1e-3) / 1e12 / peak},
+        "k_tail+k_finish": {"ray_steps": rows, "ms": lms,
+                            "frac": rows * avg / (lms * 1e-3) / 1e12 / peak if lms > 0 else None}}
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": measured_traffic() if precision == "fp64" else None,
+            "kernel": "trace launch: k_start + k_trace + k_tail + k_finish (" + precision + ")",
+            "kernel_ms_avg": kms, "flops_per_launch": flops, "flops_per_ray_step_avg": avg,
+            "flops_per_ray_step": FLOPS_PER_STEP,
+            "peak_note": ("FP64 vector peak" if precision == "fp64" else
+                          "FP32 vector without packed math (the kernels use none) = FP64 rate"),
+            "per_kernel": per_kernel}
 
 
 def main():
@@ -175,93 +224,66 @@ def main():
     steps_per_trace = fp64["ray_steps"] / a.steps
     ms_per_step = fp64["elapsed"] / a.steps * 1e3
     value = steps_per_trace / (ms_per_step / 1e3)
-    kms = float(np.mean(fp64["kernel_ms"]))
-    achieved = steps_per_trace * FLOPS_PER_STEP_ANISO / (kms * 1e-3) / 1e12
 
     res64 = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in fp64["out"].items()}
     res32 = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in mixed["out"].items()}
+    e, az, f, m = wl.fan.expand()
+    roof = roofline(res64, m, fp64, wl, "fp64")
+    roof32 = roofline(res32, m, mixed, wl, "mixed")
 
     cpu = None
     cpu_1thread = None
     accuracy = {}
     if not a.no_cpu:
         from oracle import oracle as O
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import classify_fp64, classify_mixed
         idx = np.arange(0, wl.fan.n_rays, a.cpu_sample_stride)
-        e, az, f, m = wl.fan.expand()
         med = O.OracleMedium.from_grid(wl.grid)
         nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        okw = dict(B0=wl.grid.B0_T, R=wl.grid.geom.earth_radius_km,
+                   tx=(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km),
+                   step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km)
+
+        def oracle_trace(ee, aa, ff, mm, nt=nthreads):
+            return O.trace(med, ee, aa, ff, mm, nthreads=nt, **okw)
         t = time.perf_counter()
-        o = O.trace(med, e[idx], az[idx], f[idx], m[idx], B0=wl.grid.B0_T,
-                    R=wl.grid.geom.earth_radius_km,
-                    tx=(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km),
-                    step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km,
-                    nthreads=nthreads)
+        o = oracle_trace(e[idx], az[idx], f[idx], m[idx])
         dt = time.perf_counter() - t
         cpu = {"value": o["total_steps"] / dt, "unit": "ray-steps/s", "cores": nthreads,
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "kind": "oracle",
                "sample": f"every {a.cpu_sample_stride}. ray of the 112,400-ray ionogram sweep "
                          f"({idx.size} rays, {o['total_steps']} ray-steps, {dt:.1f} s, "
                          f"plain FP64 C, OpenMP over rays)"}
         # one host thread on a bounded sample (every 64th ray)
         idx1 = np.arange(0, wl.fan.n_rays, 64)
         t = time.perf_counter()
-        o1 = O.trace(med, e[idx1], az[idx1], f[idx1], m[idx1], B0=wl.grid.B0_T,
-                     R=wl.grid.geom.earth_radius_km,
-                     tx=(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km),
-                     step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km, nthreads=1)
+        o1 = oracle_trace(e[idx1], az[idx1], f[idx1], m[idx1], 1)
         dt1 = time.perf_counter() - t
         cpu_1thread = {"value": o1["total_steps"] / dt1, "unit": "ray-steps/s", "cores": 1,
                        "sample": f"every 64th ray ({idx1.size} rays, {o1['total_steps']} ray-steps, "
                                  f"{dt1:.1f} s)"}
-        same = (res64["status"][idx] == o["status"])
-        scale = lambda k, fl: np.abs(res64[k][idx][same] - o[k][same]) / np.maximum(np.abs(o[k][same]), fl)
-        relv = np.max([scale(k, 1.0) for k in ("group_km", "phase_km", "range_km", "az_dev_deg")], axis=0)
-        accuracy["fp64_max_rel_vs_oracle"] = float(relv.max())
-        accuracy["fp64_median_rel_vs_oracle"] = float(np.median(relv))
-        accuracy["fp64_rays_over_1e-9_rel"] = int((relv > 1e-9).sum())
-        accuracy["fp64_status_mismatch"] = int((~same).sum())
-        same32 = (res32["status"][idx] == o["status"]) & (o["status"] != 3)
-        for k in ("group_km", "range_km", "az_dev_deg"):
-            d = res32[k][idx][same32] - o[k][same32]
-            accuracy[f"mixed_{k}_max_all"] = float(np.abs(d).max())
-            accuracy[f"mixed_{k}_rms_all"] = float(np.sqrt(np.mean(d * d)))
-        accuracy["mixed_status_mismatch"] = int((~same32 & (o["status"] != 3)).sum())
-        accuracy["sample_rays"] = int(idx.size)
-        # FP32 evaluation perturbs every right-hand side at the 1e-7 level: a
-        # ray whose FP64 outputs already move by more than the tolerance when
-        # its elevation moves by 1e-6 deg or its frequency by 5e-8 (X by
-        # 1e-7) -- near the penetration boundary, near reflection -- is
-        # counted apart.  Probed on every 8th sampled ray.
-        sub = np.arange(0, idx.size, 8)
-        k_idx = idx[sub]
-        pe = np.concatenate([e[k_idx] - 1e-6, e[k_idx] + 1e-6, e[k_idx], e[k_idx]])
-        pf = np.concatenate([f[k_idx], f[k_idx], f[k_idx] * (1 - 5e-8), f[k_idx] * (1 + 5e-8)])
-        rep4 = lambda v: np.concatenate([v[k_idx]] * 4)
-        pr = O.trace(med, pe, rep4(az), pf, rep4(m), B0=wl.grid.B0_T,
-                     R=wl.grid.geom.earth_radius_km,
-                     tx=(wl.fan.tx_lat_deg, wl.fan.tx_lon_deg, wl.fan.tx_h_km),
-                     step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km,
-                     nthreads=nthreads)
-        ns = sub.size
-        ill = np.zeros(ns, dtype=bool)
-        for half in range(4):
-            sl = slice(half * ns, (half + 1) * ns)
-            ill |= pr["status"][sl] != o["status"][sub]
-            ill |= np.abs(pr["range_km"][sl] - o["range_km"][sub]) > 0.1
-            ill |= np.abs(pr["group_km"][sl] - o["group_km"][sub]) > 0.1
-            ill |= np.abs(pr["az_dev_deg"][sl] - o["az_dev_deg"][sub]) > 0.001
-        good = ~ill & (res32["status"][k_idx] == o["status"][sub]) & (o["status"][sub] != 3)
-        for k in ("group_km", "range_km", "az_dev_deg"):
-            d = res32[k][k_idx][good] - o[k][sub][good]
-            accuracy[f"mixed_{k}_max"] = float(np.abs(d).max())
-            accuracy[f"mixed_{k}_rms"] = float(np.sqrt(np.mean(d * d)))
-        within = good & (np.abs(res32["range_km"][k_idx] - o["range_km"][sub]) <= 0.1) & \
-            (np.abs(res32["group_km"][k_idx] - o["group_km"][sub]) <= 0.1) & \
-            (np.abs(res32["az_dev_deg"][k_idx] - o["az_dev_deg"][sub]) <= 0.001)
-        accuracy["mixed_conditioned_within_tolerance"] = int(within.sum())
-        accuracy["mixed_conditioned_rays"] = int(good.sum())
-        accuracy["mixed_ill_conditioned_rays"] = int(ill.sum())
-        accuracy["mixed_tolerance"] = "0.1 km ground range and group path, 0.001 deg azimuth"
+        rays = (e[idx], az[idx], f[idx], m[idx])
+        # every ray of the sample classified: within the 1e-9 gate, or
+        # ill-conditioned (and within 1e-6 of an oracle result), or a failure
+        r64 = classify_fp64(res64, o, rays, oracle_trace, gpu_idx=idx)
+        accuracy["fp64"] = {
+            "rays": r64["n"], "within_1e-9": r64["n_within"],
+            "ill_conditioned": len(r64["ill_conditioned"]), "failures": len(r64["failures"]),
+            "max_rel_within": r64["worst_rel"], "median_rel_within": r64["median_rel"],
+            "ill_conditioned_max_rel_vs_nearest_oracle":
+                max([x[4] for x in r64["ill_conditioned"]], default=0.0),
+            "gate": "|d| <= 1e-9 max(|ref|, 1 km or 1 deg), same status and step count; "
+                    "ill-conditioned: oracle outputs move > 1e-7 when the elevation moves by "
+                    "1e-10 relative"}
+        r32 = classify_mixed(res32, o, rays, oracle_trace, gpu_idx=idx)
+        accuracy["mixed"] = {k: v for k, v in r32.items() if k != "failures"}
+        accuracy["mixed"]["tolerance"] = ("0.1 km ground range and group path, 0.001 deg azimuth; "
+                                          "ill-conditioned at FP32 level: oracle outputs move beyond "
+                                          "that when the elevation moves by 1e-6 deg or the "
+                                          "frequency by a factor 1 +- 5e-8")
+        accuracy["fp64_failures_first"] = r64["failures"][:3]
+        accuracy["mixed_failures_first"] = r32["failures"][:3]
 
     lat = np.array(fan64["walls"]) * 1e3
     lat32 = np.array(fan32["walls"]) * 1e3
@@ -284,11 +306,7 @@ def main():
                    "ray_steps_per_step": int(steps_per_trace), "field": "axial dipole 3.12e-5 T",
                    "modes": "O+X", "step_km": wl.step_km, "exit_km": wl.exit_km,
                    "max_group_km": wl.max_group_km},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS,
-                     "traffic": measured_traffic(),
-                     "kernel": "trace launch: k_start + k_trace<double,0> + k_tail<double,0> + k_finish",
-                     "kernel_ms_avg": kms, "flops_per_ray_step": FLOPS_PER_STEP_ANISO},
+        "roofline": roof,
         "tuning": {"fp64": tune64, "mixed": tune32},
         "cpu_baseline": cpu,
         "cpu_oracle_1thread": cpu_1thread,
@@ -299,7 +317,8 @@ def main():
         "accuracy": accuracy,
         "mixed": {"value": mixed["ray_steps"] / mixed["elapsed"],
                   "kernel_ms_avg": float(np.mean(mixed["kernel_ms"])),
-                  "speedup_vs_fp64": (mixed["ray_steps"] / mixed["elapsed"]) / value},
+                  "speedup_vs_fp64": (mixed["ray_steps"] / mixed["elapsed"]) / value,
+                  "roofline": roof32},
         "aniso_fan_24576": {
             "fp64_ray_steps_per_s": fan64["ray_steps"] / fan64["elapsed"],
             "mixed_ray_steps_per_s": fan32["ray_steps"] / fan32["elapsed"],

@@ -185,6 +185,12 @@ typedef struct {
     int32_t *traj_count;
     int64_t total_steps;    /* out: sum of n_steps over the fan            */
     double kernel_ms;       /* out: device time of the launch's kernels    */
+    /* out (rt_trace only): how the launch ran -- RK4 steps taken one lane
+     * per ray, on promotion rows and on 16-lane rows after the hand-off (or
+     * of the in-wave switch), summing to total_steps; device time of the
+     * ray-start and one-lane kernels, then of the tail and finish kernels */
+    int64_t steps_one_lane, steps_promoted, steps_rows;
+    double trace_ms, tail_ms;
 } rt_results;
 
 /* Create a context on HIP device `device` issuing work on `hip_stream`
@@ -204,8 +210,15 @@ rt_status rt_grid_create(rt_ctx *ctx, const rt_grid_geom *geom, const void *valu
                          int32_t values_mem, rt_grid **out);
 void rt_grid_destroy(rt_grid *grid);
 
-/* Set (or with d == NULL / B0 == 0 clear) the dipole field of a grid,
- * stored by value.  RT_E_UNSUPPORTED for a tilted dipole. */
+/* Geomagnetic model (Sec. II-C, the field input of the preprocessing
+ * module; it enters the refractive index through Y = f_H / f of eq.
+ * appleton, with Y_L and Y_T its components along and across the wave
+ * normal).  Set (or with d == NULL / B0 == 0 clear) the dipole field of a
+ * grid, stored by value on the grid handle; later traces of the grid use
+ * it.  The field is a centred axial dipole: B_r = -2 B0 (R/r)^3 cos(theta),
+ * B_theta = -B0 (R/r)^3 sin(theta), B_phi = 0 in local components (it
+ * points down in the northern hemisphere).  RT_E_INVALID for a negative or
+ * non-finite B0; RT_E_UNSUPPORTED for a tilted dipole (pole_lat_deg != 90). */
 rt_status rt_field_set(rt_grid *grid, const rt_dipole *d);
 
 /* Trace every ray of a fan through a grid (main processing module of
@@ -213,7 +226,10 @@ rt_status rt_field_set(rt_grid *grid, const rt_dipole *d);
  * stream.  RT_E_INVALID on bad options or fan values; RT_E_UNSUPPORTED if
  * a frequency is at or below the largest electron gyrofrequency of the
  * field (Y >= 1), or the transmitter is not below the grid bottom.
- * Per-ray failures are statuses, not call failures.  An empty fan is a
+ * Per-ray failures are statuses, not call failures.  RT_E_DEVICE on a HIP
+ * error, or if the launch itself went wrong: a promotion wait that timed
+ * out, or a ray that no trace kernel finished (such rays keep status -1
+ * and NaN outputs; no output of a failed call is valid).  An empty fan is a
  * no-op returning RT_OK. */
 rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
                    const rt_trace_opts *opts, rt_results *res);

@@ -16,18 +16,28 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rtgd_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+COUNT_SRC = os.path.join(HERE, "op_count.cpp")
+COUNT_LIB = os.path.join(HERE, "liboracle_count.so")
 
 GRID, CHAPMAN, QP, GRID_CR = 0, 1, 2, 3
 GROUND, ESCAPE, MAX_PATH, NUMERIC = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc: FP64, no fast-math, no FMA contraction."""
+    """Compile the oracle with gcc: FP64, no fast-math, no FMA contraction;
+    and its operation-counting build (op_count.cpp, the same source as C++
+    with a counting number type, no OpenMP)."""
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-fno-fast-math", "-o", LIB + ".tmp", SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)
+    if force or not os.path.exists(COUNT_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-Wno-unknown-pragmas", "-fPIC", "-shared",
+               "-ffp-contract=off", "-fno-fast-math", "-I", HERE, "-o", COUNT_LIB + ".tmp",
+               COUNT_SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(COUNT_LIB + ".tmp", COUNT_LIB)
     return LIB
 
 
@@ -70,36 +80,68 @@ _DP = ctypes.POINTER(ctypes.c_double)
 _IP = ctypes.POINTER(ctypes.c_int)
 
 
+def _bind(L):
+    L.or_gd_weights.argtypes = [ctypes.c_double, _DP, _DP]
+    L.or_cr_weights.argtypes = [ctypes.c_double, _DP, _DP]
+    L.or_medium_eval.argtypes = [ctypes.POINTER(Medium), ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, _DP]
+    L.or_dipole.argtypes = [ctypes.c_double] * 5 + [_DP, _DP, _DP]
+    L.or_appleton.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_int, _DP]
+    L.or_appleton.restype = ctypes.c_int
+    L.or_hamiltonian.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field),
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, _DP,
+                                 ctypes.POINTER(Ham)]
+    L.or_hamiltonian.restype = ctypes.c_int
+    L.or_rhs.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field), ctypes.c_double,
+                         ctypes.c_double, ctypes.c_int, _DP, _DP]
+    L.or_rhs.restype = ctypes.c_int
+    L.or_launch.argtypes = [ctypes.POINTER(Opts), ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, _DP]
+    L.or_launch.restype = ctypes.c_double
+    L.or_trace.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field),
+                           ctypes.POINTER(Opts), ctypes.c_int, _DP, _DP, _DP, _IP, _DP,
+                           _IP, _IP, _DP, ctypes.c_int, _IP]
+    L.or_trace.restype = ctypes.c_longlong
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
-        L.or_gd_weights.argtypes = [ctypes.c_double, _DP, _DP]
-        L.or_cr_weights.argtypes = [ctypes.c_double, _DP, _DP]
-        L.or_medium_eval.argtypes = [ctypes.POINTER(Medium), ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_double, _DP]
-        L.or_dipole.argtypes = [ctypes.c_double] * 5 + [_DP, _DP, _DP]
-        L.or_appleton.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                  ctypes.c_int, _DP]
-        L.or_appleton.restype = ctypes.c_int
-        L.or_hamiltonian.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field),
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, _DP,
-                                     ctypes.POINTER(Ham)]
-        L.or_hamiltonian.restype = ctypes.c_int
-        L.or_rhs.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field), ctypes.c_double,
-                             ctypes.c_double, ctypes.c_int, _DP, _DP]
-        L.or_rhs.restype = ctypes.c_int
-        L.or_launch.argtypes = [ctypes.POINTER(Opts), ctypes.c_double, ctypes.c_double,
-                                ctypes.c_double, _DP]
-        L.or_launch.restype = ctypes.c_double
-        L.or_trace.argtypes = [ctypes.POINTER(Medium), ctypes.POINTER(Field),
-                               ctypes.POINTER(Opts), ctypes.c_int, _DP, _DP, _DP, _IP, _DP,
-                               _IP, _IP, _DP, ctypes.c_int, _IP]
-        L.or_trace.restype = ctypes.c_longlong
-        _lib = L
+        _lib = _bind(ctypes.CDLL(LIB))
     return _lib
+
+
+_count_lib = None
+
+
+def count_lib():
+    """The operation-counting build: the same entry points (serial), plus
+    or_count_reset() and or_count_get(out[4]) = {add/sub, mul, div, libm}."""
+    global _count_lib
+    if _count_lib is None:
+        if not os.path.exists(COUNT_LIB):
+            build(force=False)
+        L = _bind(ctypes.CDLL(COUNT_LIB))
+        L.or_count_get.argtypes = [ctypes.POINTER(ctypes.c_ulonglong)]
+        _count_lib = L
+    return _count_lib
+
+
+def counted(fn, *args):
+    """Run fn(*args) and return (result, ops) with ops = {add, mul, div, lib,
+    total} counted by the counting build (fn must call count_lib())."""
+    L = count_lib()
+    L.or_count_reset()
+    r = fn(*args)
+    c = (ctypes.c_ulonglong * 4)()
+    L.or_count_get(c)
+    ops = dict(add=int(c[0]), mul=int(c[1]), div=int(c[2]), lib=int(c[3]))
+    ops["total"] = sum(ops.values())
+    return r, ops
 
 
 def _dp(a):
@@ -207,9 +249,10 @@ OUT_NAMES = ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km",
 
 def trace(med: OracleMedium, elev, az, freq, mode=None, B0=0.0, R=6371.0,
           tx=(30.0, 110.0, 0.0), step=1.0, max_group=4000.0, exit_h=500.0,
-          traj_stride=0, traj_per_ray=0, nthreads=0):
+          traj_stride=0, traj_per_ray=0, nthreads=0, counting=False):
     """Trace rays given per-ray elevation/azimuth (deg), frequency (MHz) and
-    mode (+1 O, -1 X).  Returns a dict of numpy arrays."""
+    mode (+1 O, -1 X).  Returns a dict of numpy arrays.  counting=True runs
+    the operation-counting build (serial; see counted())."""
     elev = np.ascontiguousarray(elev, dtype=np.float64)
     n = elev.size
     az = np.ascontiguousarray(np.broadcast_to(az, (n,)), dtype=np.float64)
@@ -226,7 +269,8 @@ def trace(med: OracleMedium, elev, az, freq, mode=None, B0=0.0, R=6371.0,
     if traj_stride > 0 and traj_per_ray > 0:
         traj = np.zeros((n, traj_per_ray, 8))
         tcount = np.zeros(n, dtype=np.int32)
-    total = lib().or_trace(ctypes.byref(med.m), ctypes.byref(fld), ctypes.byref(opts), n,
+    L = count_lib() if counting else lib()
+    total = L.or_trace(ctypes.byref(med.m), ctypes.byref(fld), ctypes.byref(opts), n,
                            _dp(elev), _dp(az), _dp(freq), _ip(mode), _dp(out7), _ip(status),
                            _ip(nsteps), _dp(traj) if traj is not None else None,
                            traj_per_ray, _ip(tcount) if tcount is not None else None)

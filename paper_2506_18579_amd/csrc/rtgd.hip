@@ -41,6 +41,7 @@ struct rt_ctx {
     void *pinned = nullptr;     // pinned host staging of fan, parameters, counters
     size_t pinned_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evm = nullptr;   // between the one-lane and the tail kernel
 };
 
 struct rt_grid {
@@ -175,9 +176,11 @@ rt_status rt_ctx_create(int32_t device, void *stream, rt_ctx **out)
     hipDeviceProp_t prop;
     if ((e = hipSetDevice(device)) != hipSuccess ||
         (e = hipGetDeviceProperties(&prop, device)) != hipSuccess ||
-        (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess) {
+        (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess ||
+        (e = hipEventCreate(&c->evm)) != hipSuccess) {
         g_create_error = std::string("device setup: ") + hipGetErrorString(e);
         if (c->ev0) (void)hipEventDestroy(c->ev0);
+        if (c->ev1) (void)hipEventDestroy(c->ev1);
         delete c;
         return RT_E_DEVICE;
     }
@@ -199,6 +202,7 @@ void rt_ctx_destroy(rt_ctx *c)
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->evm) (void)hipEventDestroy(c->evm);
     delete c;
 }
 
@@ -353,10 +357,16 @@ constexpr int kDefaultPromoteAge = 0;
 // step counter per segment).
 struct Counters {
     int32_t head, trunc, live, n_handoff;
-    int32_t pad0[28];          // the promotion counters on cache lines of their own
+    int32_t unfinished;        // rays left without a final status (k_finish)
+    int32_t pad0[27];          // the promotion counters on cache lines of their own
     int32_t promo_push, promo_pop, promo_live, producers_alive, promo_err;
     int32_t pad1[27];
+    // RK4 ray-steps by phase: one lane per ray, promotion rows, 16-lane rows
+    // after the hand-off (or of the in-wave switch)
+    unsigned long long phase_steps[3];
+    int32_t pad2[10];
 };
+static_assert(sizeof(Counters) % 64 == 0, "counters fill whole cache lines");
 
 // Workspace layout of a launch, the same on the device and in host staging
 // (the hand-off buffer is device only): fan axes | segments | parameter
@@ -532,6 +542,8 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.promo_live = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_live));
     P.producers_alive = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, producers_alive));
     P.promo_err = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_err));
+    P.unfinished = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, unfinished));
+    P.phase_steps = reinterpret_cast<unsigned long long *>(cnt + offsetof(Counters, phase_steps));
     P.promo_ids = reinterpret_cast<int32_t *>(dev + lay.ids);
     // Longest wait of an idle promotion wave while one-lane waves still run,
     // in wall-clock ticks: far above the one-lane waves' worst case (every
@@ -559,7 +571,7 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
 // which a replayed upload must not see).  Events (optional) bracket the
 // kernels.
 rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char *dev, char *host,
-                      hipEvent_t ev0, hipEvent_t ev1, char *readback = nullptr)
+                      hipEvent_t ev0, hipEvent_t ev1, char *readback = nullptr, hipEvent_t evm = nullptr)
 {
     const Layout lay = job_layout(job);
     std::memset(host + lay.seg, 0, lay.host_bytes - lay.seg);
@@ -654,12 +666,25 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     if (ev0) HIP_OR_FAIL(ctx, hipEventRecord(ev0, stream));
     HIP_OR_FAIL(ctx, hipLaunchKernel(ks, per_ray, dim3(64), args, 0, stream));
     HIP_OR_FAIL(ctx, hipLaunchKernel(kt, dim3(waves), dim3(64), args, 0, stream));
+    if (evm) HIP_OR_FAIL(ctx, hipEventRecord(evm, stream));
     if (job.tail > 0)
         HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 3) / 4), dim3(64), args, 0, stream));
     HIP_OR_FAIL(ctx, hipLaunchKernel(kf, per_ray, dim3(64), args, 0, stream));
     if (ev1) HIP_OR_FAIL(ctx, hipEventRecord(ev1, stream));
     HIP_OR_FAIL(ctx, hipMemcpyAsync(readback ? readback : host + lay.cnt, dev + lay.cnt, lay.hand - lay.cnt,
                                     hipMemcpyDeviceToHost, stream));
+    return RT_OK;
+}
+
+// The launch error the counters report, if any: a promotion wait that
+// timed out, or rays that no trace kernel finished (their outputs are NaN
+// and their status -1).  Either means a fault of the launch, never a
+// property of the rays.
+rt_status launch_error(rt_ctx *ctx, const Counters &c)
+{
+    if (c.promo_err) return fail(ctx, RT_E_DEVICE, "promotion queue timed out");
+    if (c.unfinished)
+        return fail(ctx, RT_E_DEVICE, std::to_string(c.unfinished) + " rays were left without a final status");
     return RT_OK;
 }
 
@@ -710,7 +735,8 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     if (st != RT_OK) return st;
     finish_job(ctx, job, *opts);
     res->total_steps = 0;
-    res->kernel_ms = 0.0;
+    res->kernel_ms = res->trace_ms = res->tail_ms = 0.0;
+    res->steps_one_lane = res->steps_promoted = res->steps_rows = 0;
     if (job.n_rays == 0) return RT_OK;
     const int64_t n64 = job.n_rays;
     if (opts->traj_stride > 0 && (!res->traj || opts->traj_capacity < n64))
@@ -747,7 +773,7 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     }
     char *pinned = static_cast<char *>(ctx->pinned);
     if ((st = enqueue_job(ctx, ctx->stream, job, static_cast<char *>(ctx->ws), pinned, ctx->ev0,
-                          ctx->ev1)) != RT_OK)
+                          ctx->ev1, nullptr, ctx->evm)) != RT_OK)
         return st;
     if (host_out) {
         for (int k = 0; k < 7; ++k)
@@ -766,12 +792,19 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.f;
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    float ms_trace = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms_trace, ctx->ev0, ctx->evm));
     Counters hc;
     std::vector<int64_t> steps;
     job_counters(job, pinned, hc, steps);
     res->total_steps = steps[0];
     res->kernel_ms = ms;
-    if (hc.promo_err) return fail(ctx, RT_E_DEVICE, "promotion queue timed out");
+    res->trace_ms = ms_trace;
+    res->tail_ms = ms - ms_trace;
+    res->steps_one_lane = int64_t(hc.phase_steps[0]);
+    res->steps_promoted = int64_t(hc.phase_steps[1]);
+    res->steps_rows = int64_t(hc.phase_steps[2]);
+    if ((st = launch_error(ctx, hc)) != RT_OK) return st;
     return hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
 }
 
@@ -1119,7 +1152,8 @@ extern "C" rt_status rt_server_poll(rt_server *srv, rt_request_info *done, int32
             Request &r = srv->reqs[sl.reqs[k]];
             r.info.total_steps = steps[k];
             r.info.kernel_ms = ms;
-            r.info.status = hc.promo_err ? RT_E_DEVICE : hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+            r.info.status = launch_error(ctx, hc) != RT_OK ? RT_E_DEVICE
+                          : hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
             r.state = 2;
             if (r.cancelled) {
                 srv->arena.release(r.off, r.bytes);
@@ -1324,8 +1358,7 @@ extern "C" rt_status rt_plan_wait(rt_plan *p, int64_t *total_steps, double *kern
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, p->ev0, p->ev1));
     if (total_steps) *total_steps = steps[0];
     if (kernel_ms) *kernel_ms = ms;
-    if (hc.promo_err) return fail(ctx, RT_E_DEVICE, "promotion queue timed out");
-    return RT_OK;
+    return launch_error(ctx, hc);
 }
 
 // ===========================================================================

@@ -84,6 +84,10 @@ struct TraceParams {
     int32_t *promo_live;       // promoted rays not yet finished or handed off
     int32_t *producers_alive;  // one-lane waves still running
     int32_t *promo_err;        // waits that timed out (reported as a launch error)
+    int32_t *unfinished;       // rays k_finish found without a final status (a launch error)
+    unsigned long long *phase_steps;   // RK4 ray-steps run one lane per ray, on promotion
+                                       // rows, on 16-lane rows after the hand-off (or the
+                                       // in-wave switch)
     int64_t idle_ticks;        // wall-clock bound of an idle promotion wave's wait
     int32_t *promo_ids;        // ray of each ticket, -1 until published (n_rays entries)
 };
@@ -299,7 +303,7 @@ __device__ __forceinline__ void finish_ray(const TraceParams<T> &P, int ray)
     }
     double o[7] = {L.gp, L.y[6], P.g.R * gam, azd, L.apogee, 90.0 - L.y[1] * kRad2Deg,
                    L.y[2] * kRad2Deg};
-    if (status == kNumeric) {
+    if (status == kNumeric || status < 0) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) o[k] = __builtin_nan("");
     }
@@ -418,6 +422,15 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParam
     return status;
 }
 
+// Add the per-lane step counts of a wave to a launch-wide counter (one
+// atomic per wave).
+__device__ __forceinline__ void add_wave_steps(unsigned long long *ctr, unsigned long long mine)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+    if (__lane_id() == 0 && mine) atomicAdd(ctr, mine);
+}
+
 // wave-aggregated atomic add (lanes with pred), returns each lane's slot
 __device__ __forceinline__ int wave_append(int32_t *counter, bool pred, int lane)
 {
@@ -445,9 +458,11 @@ __device__ __forceinline__ void run_rows(const TraceParams<T> &P, const TracePar
     sc.clear();
     sc.pa = piece<T, IP>((lane >> 2) & 3);
     sc.pb = piece<T, IP>(lane & 3);
+    unsigned long long nsteps = 0;
     for (;;) {
         if (__ballot(ray >= 0) == 0ull) break;
         if (ray >= 0) {
+            nsteps += lead ? 1u : 0u;
             int st = advance<T, IP, 16, UNROLL>(P, Pp, ray, L, lead, sc);
             if (st >= 0) {
                 if (lead) retire(P, ray, L, st);
@@ -455,6 +470,7 @@ __device__ __forceinline__ void run_rows(const TraceParams<T> &P, const TracePar
             }
         }
     }
+    add_wave_steps(P.phase_steps + 2, nsteps);
 }
 
 // Move the (at most four) live rays of the wave, marked in `live`, onto
@@ -586,6 +602,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
     Lane L;
     StencilCache<T, 1> sc;
     sc.clear();
+    unsigned long long nsteps = 0;
     for (int iter = 0;; ++iter) {
         bool need = (ray == -1);
         if (__ballot(need)) {
@@ -640,6 +657,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
         if (P.promote_cap > 0 && (iter & 31) == 0) promote(P, ray, L, lane);
         int st = -1;
         if (ray >= 0) {
+            ++nsteps;
             st = advance<T, IP, 1>(P, Pp, ray, L, true, sc);
             if (st >= 0) {
                 retire(P, ray, L, st);
@@ -649,7 +667,16 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
         unsigned long long fin = __ballot(st >= 0);
         if (lane == 0 && fin && P.handoff_threshold > 0) atomicSub(P.live, __popcll(fin));
     }
-    if (lane == 0 && P.promote_cap > 0) atomicSub(P.producers_alive, 1);
+    add_wave_steps(P.phase_steps, nsteps);
+    // Release: the wave's earlier tickets (promo_push) and records are
+    // visible to any promotion wave that reads the decremented count with
+    // acquire.  The fence covers every lane's operations (a wave waits on
+    // its own memory counters), then one lane decrements.
+    if (P.promote_cap > 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0)
+            __hip_atomic_fetch_add(P.producers_alive, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
     // after the one-lane loop, so that its stencil cache is dead here
     if (to_rows) {
         gather_rows(to_rows, ray, L);
@@ -730,6 +757,7 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
     bool closing = false;
     bool idling = false;
     long long idle_t0 = 0;
+    unsigned long long nsteps = 0;
     for (int iter = 0;; ++iter) {
         // The shared counters are polled every iteration while the whole wave
         // is idle, and every 32nd while a row runs: a poll is a memory round
@@ -769,6 +797,7 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
         if (__ballot(ray >= 0) != 0ull) {
             int st = -1;
             if (ray >= 0) {
+                nsteps += lead ? 1u : 0u;
                 st = advance<T, IP, 16, true>(P, Pp, ray, L, lead, sc);
                 if (st >= 0) {
                     if (lead) retire(P, ray, L, st);
@@ -782,11 +811,15 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             }
             idling = false;
         } else {
+            // Exit check, ordered: the count of running one-lane waves is read
+            // with acquire first.  Once it reads 0, every producer's tickets
+            // were pushed before its release decrement, so the push count read
+            // after it is final and no ticket can be left unclaimed.
             int alive = 0, popped = 0, pushed = 0;
             if (lane == 0) {
-                alive = __hip_atomic_load(P.producers_alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                popped = __hip_atomic_load(P.promo_pop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                alive = __hip_atomic_load(P.producers_alive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                 pushed = __hip_atomic_load(P.promo_push, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                popped = __hip_atomic_load(P.promo_pop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             alive = __shfl(alive, 0);
             popped = __shfl(popped, 0);
@@ -803,6 +836,7 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             __builtin_amdgcn_s_sleep(32);
         }
     }
+    add_wave_steps(P.phase_steps + 1, nsteps);
 }
 
 // Starting state of every launch ray (one thread per ray).
@@ -830,11 +864,17 @@ __device__ __forceinline__ void finish_body(const TraceParams<T> &P)
     const bool valid = ray < P.n_rays;
     int seg = 0;
     unsigned long long steps = 0;
+    bool lost = false;
     if (valid) {
+        lost = P.rec[ray].status < 0;
         finish_ray(P, ray);
         seg = P.rec[ray].L.seg;
         steps = (unsigned long long)P.rec[ray].L.steps;
     }
+    // A ray still without a final status was never finished by a trace
+    // kernel: its outputs are not valid, and the launch reports an error.
+    const unsigned long long lm = __ballot(lost);
+    if (lm && int(threadIdx.x) == __ffsll((long long)lm) - 1) atomicAdd(P.unfinished, __popcll(lm));
     unsigned long long todo = __ballot(valid);
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;

@@ -69,7 +69,9 @@ class Results(ctypes.Structure):
                 ("az_dev_deg", _DP), ("apogee_km", _DP), ("land_lat_deg", _DP),
                 ("land_lon_deg", _DP), ("status", _IP), ("n_steps", _IP),
                 ("traj", _DP), ("traj_count", _IP), ("total_steps", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("steps_one_lane", ctypes.c_int64),
+                ("steps_promoted", ctypes.c_int64), ("steps_rows", ctypes.c_int64),
+                ("trace_ms", ctypes.c_double), ("tail_ms", ctypes.c_double)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -318,7 +320,9 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
 
     Returns a dict of per-ray arrays (numpy on the host, or torch tensors on
     the device with device_results=True; pass `out` to reuse device
-    tensors), plus total_steps and kernel_ms."""
+    tensors), plus total_steps, kernel_ms and how the launch ran:
+    phase_steps (one lane, promotion rows, 16-lane rows), trace_ms and
+    tail_ms."""
     fa = FanArgs(fan)
     n = ctypes.c_int64(0)
     st = lib().rt_fan_count(ctypes.byref(fa.s), ctypes.byref(n))
@@ -360,6 +364,9 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
     res = dict(out)
     res["total_steps"] = int(r.total_steps)
     res["kernel_ms"] = float(r.kernel_ms)
+    res["phase_steps"] = (int(r.steps_one_lane), int(r.steps_promoted), int(r.steps_rows))
+    res["trace_ms"] = float(r.trace_ms)
+    res["tail_ms"] = float(r.tail_ms)
     res["truncated"] = st == RT_W_TRAJ_TRUNCATED
     return res
 

@@ -21,3 +21,19 @@ def orc():
         O.build()
     O.lib()
     return O
+
+
+@pytest.fixture(scope="session")
+def ionogram_sweep():
+    """The 112,400-ray oblique-ionogram sweep (grid, fan, limits)."""
+    from paper_2506_18579_amd import synth
+    return synth.ionogram_workload(0)
+
+
+@pytest.fixture(scope="session")
+def ionogram_sweep_oracle(orc, ionogram_sweep):
+    """Oracle results for every ray of the sweep (traced once per session,
+    OpenMP over all host cores) and the re-tracing function of the sweep."""
+    from parity import oracle_tracer
+    tr = oracle_tracer(orc, ionogram_sweep)
+    return tr(*ionogram_sweep.fan.expand()), tr

@@ -115,8 +115,9 @@ def test_struct_layout_matches_header(rt):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(rt_grid_geom), sizeof(rt_fan), sizeof(rt_trace_opts),
          sizeof(rt_results), sizeof(rt_dipole));
-  printf("%zu %zu %zu %zu\n", offsetof(rt_grid_geom, lat0_deg), offsetof(rt_fan, az_deg),
-         offsetof(rt_trace_opts, results_mem), offsetof(rt_results, kernel_ms));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(rt_grid_geom, lat0_deg), offsetof(rt_fan, az_deg),
+         offsetof(rt_trace_opts, results_mem), offsetof(rt_results, kernel_ms),
+         offsetof(rt_results, tail_ms));
   return 0;
 }
 '''
@@ -131,7 +132,7 @@ int main(void) {
     want = [ctypes.sizeof(rt.GridGeom), ctypes.sizeof(rt.Fan), ctypes.sizeof(rt.TraceOpts),
             ctypes.sizeof(rt.Results), ctypes.sizeof(rt.Dipole),
             rt.GridGeom.lat0_deg.offset, rt.Fan.az_deg.offset, rt.TraceOpts.results_mem.offset,
-            rt.Results.kernel_ms.offset]
+            rt.Results.kernel_ms.offset, rt.Results.tail_ms.offset]
     assert got == want
 
 

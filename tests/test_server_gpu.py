@@ -5,8 +5,10 @@ pushed through rt_server_* with several slots, so that requests overlap on
 the device and later ones are admitted as slots and arena memory free up.
 Every request's per-ray outputs must equal, bit for bit, those of the same
 fan traced alone with rt_trace (the per-ray arithmetic does not depend on
-what else runs).  Admission by memory, cancellation and the error paths are
-checked too.
+what else runs), and served results are checked against the FP64 oracle
+directly: a seeded sample of every request (every ray of the ionogram
+requests, and their extracted traces), in both precisions.  Admission by
+memory, cancellation and the error paths are checked too.
 """
 import time
 
@@ -14,6 +16,8 @@ import numpy as np
 import pytest
 
 from paper_2506_18579_amd import synth
+
+from parity import classify_mixed, compare, oracle_tracer
 
 pytestmark = pytest.mark.gpu
 
@@ -191,3 +195,73 @@ def test_ionogram_requests_in_the_mix(rt, ctx, grids):
             pts, cnt = rt.ionogram(ctx, r["fan"], alone, 1200.0, 8)
             mp, mc = out["results"][k]["ionogram"]
             assert np.array_equal(cnt, mc) and np.array_equal(pts, mp, equal_nan=True)
+
+
+def _served_mix():
+    """A Poisson mix of fan and ionogram requests, plus fans whose azimuth
+    span crosses +-180 deg (pointing away from the grid box) and a fan from
+    the box's south-west corner heading out of it."""
+    reqs = synth.serving_requests(18, seed=23, n_snapshots=2, max_rays=3000, qps=1e9,
+                                  ionogram_fraction=0.25)
+    extra = [(30.0, 110.0, np.linspace(4.0, 40.0, 12), np.linspace(170.0, 190.0, 5), 8.5, (1, -1)),
+             (30.0, 110.0, np.linspace(10.0, 60.0, 9), np.linspace(-185.0, -175.0, 3), 13.0, (-1,)),
+             (9.0, 89.0, np.linspace(5.0, 30.0, 6), np.linspace(200.0, 300.0, 6), 6.0, (1, -1))]
+    for k, (la, lo, el, az, f, modes) in enumerate(extra):
+        reqs.append(dict(id=100 + k, t_arrive=0.0, snapshot=k % 2,
+                         fan=synth.Fan(la, lo, 0.0, el, az, np.array([f]), modes)))
+    return reqs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_served_requests_match_oracle(rt, ctx, orc, grids, precision):
+    """Requests served concurrently (4 slots, batched launches) against the
+    FP64 oracle: FP64 at the 1e-9 gate, mixed at 0.1 km / 0.001 deg (rays
+    ill-conditioned at FP32 level counted apart).  Fan requests: a seeded
+    sample of 12 rays plus the first and the last; ionogram requests: every
+    ray, and (FP64) the extracted traces against the oracle's extraction."""
+    from paper_2506_18579_amd import serve
+    reqs = _served_mix()
+    assert sum("ionogram" in r for r in reqs) >= 3
+    assert any(np.any(np.abs(r["fan"].az_deg) > 150.0) for r in reqs)
+    srv = rt.Server(ctx, n_slots=4, mem_budget_bytes=64 << 20)
+    try:
+        out = serve.replay(srv, grids, reqs, opts(precision), keep_results=True)
+    finally:
+        srv.close()
+    snaps = [synth.ionosphere_grid(synth.GEOM_ANISO, seed) for seed in (0, 1)]
+    rng = np.random.default_rng(5)
+    n_ill = n_checked = 0
+    for k, r in enumerate(reqs):
+        o_kw = dict(opts(precision), **r.get("opts", {}))
+        wl = synth.Workload("served", snaps[r["snapshot"]], r["fan"], o_kw["step_km"],
+                            o_kw["max_group_km"], o_kw["exit_h_km"])
+        got = out["results"][k]
+        n = got["status"].size
+        assert n == r["fan"].n_rays
+        if "ionogram" in r or n <= 14:
+            idx = np.arange(n)
+        else:
+            idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 12, replace=False)]))
+        e, a, f, m = r["fan"].expand()
+        rays = (e[idx], a[idx], f[idx], m[idx])
+        tr = oracle_tracer(orc, wl)
+        o = tr(*rays)
+        if precision == "fp64":
+            rep = compare(got, o, rays, tr, gpu_idx=idx)
+            n_ill += len(rep["ill_conditioned"])
+            if "ionogram" in r:
+                io = r["ionogram"]
+                pts, cnt = orc.ionogram(o, r["fan"].elev_deg, len(r["fan"].freq_mhz), 2,
+                                        io["range_km"], io["max_points"])
+                gp, gc = got["ionogram"]
+                if not rep["ill_conditioned"]:
+                    assert np.array_equal(gc, cnt)
+                    assert np.allclose(gp, pts, rtol=1e-8, atol=1e-8)
+        else:
+            rep = classify_mixed(got, o, rays, tr, gpu_idx=idx)
+            assert rep["n_fail"] == 0, (k, rep["failures"][:3])
+            n_ill += rep["n_ill"]
+        n_checked += idx.size
+    print(f"served {len(reqs)} requests ({precision}): {n_checked} rays checked against the oracle, "
+          f"{n_ill} ill-conditioned")
+    assert n_ill <= 0.05 * n_checked
