@@ -234,6 +234,29 @@ rt_status rt_field_set(rt_grid *grid, const rt_dipole *d);
 rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
                    const rt_trace_opts *opts, rt_results *res);
 
+/* For callers that cannot allocate device or pinned memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * rt_trace with every buffer the launch needs beyond the caller's inputs and
+ * outputs -- ray records, hand-off records, tickets, counters, the staged fan
+ * and parameter block -- taken from a scratch region of RT_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device from the first context on it until
+ * the process ends, and host staging held by the context.  The successful
+ * path calls no hipMalloc, hipFree, hipHostMalloc or other allocating
+ * routine.  Same arguments, results and errors as rt_trace, within these
+ * limits (RT_E_INVALID beyond them, before anything is launched):
+ * opts->results_mem must be RT_MEM_DEVICE (every non-NULL array of res is
+ * device memory), no trajectories (traj_stride 0), at most
+ * RT_NOALLOC_MAX_RAYS rays and RT_NOALLOC_MAX_AXIS fan axis values
+ * (n_elev + n_az + n_freq).  Every call on one GPU uses that GPU's one scratch
+ * region, whose contents the next call overwrites: calls that overlap on one
+ * GPU (several contexts or threads) race, and the caller must serialize
+ * them.  The call is synchronous, like rt_trace. */
+#define RT_NOALLOC_SCRATCH_BYTES (40 << 20)
+#define RT_NOALLOC_MAX_RAYS 131072
+#define RT_NOALLOC_MAX_AXIS 4096
+rt_status rt_trace_noalloc(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                           const rt_trace_opts *opts, rt_results *res);
+
 /* Synthetic oblique ionogram from a traced frequency x elevation sweep
  * (Sec. IV-B-4: joint frequency-elevation scanning).  `fan` is the fan that
  * produced `res`: one azimuth (n_az == 1), elevations strictly increasing.

@@ -42,6 +42,11 @@ struct rt_ctx {
     size_t pinned_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evm = nullptr;   // between the one-lane and the tail kernel
+    // rt_trace_noalloc: the device's scratch region (address of `scratch`
+    // on this context's device) and host staging of the fan, segment,
+    // parameter block and counters, sized for its limits
+    char *scratch = nullptr;
+    alignas(256) char noalloc_host[(RT_NOALLOC_MAX_AXIS * 8 + 16384 + 255) / 256 * 256];
 };
 
 struct rt_grid {
@@ -52,10 +57,37 @@ struct rt_grid {
     double B0 = 0.0;
 };
 
+// Scratch region of rt_trace_noalloc: one per device (each device holds its
+// own copy of a __device__ array), alive until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: on the host it is a
+// stand-in, not a device address.  Its device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) char scratch[RT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 // message of the last failed rt_ctx_create on this thread
 thread_local std::string g_create_error;
+
+// device address of `scratch` on each device (nullptr until first looked up)
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;
+
+hipError_t scratch_address(int device, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the current device's copy
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<char *>(p);
+    *out = static_cast<char *>(p);
+    return hipSuccess;
+}
 
 rt_status fail(rt_ctx *ctx, rt_status code, const std::string &msg)
 {
@@ -181,9 +213,13 @@ rt_status rt_ctx_create(int32_t device, void *stream, rt_ctx **out)
         g_create_error = std::string("device setup: ") + hipGetErrorString(e);
         if (c->ev0) (void)hipEventDestroy(c->ev0);
         if (c->ev1) (void)hipEventDestroy(c->ev1);
+        if (c->evm) (void)hipEventDestroy(c->evm);
         delete c;
         return RT_E_DEVICE;
     }
+    // the no-allocation scratch region of this device (only rt_trace_noalloc
+    // needs it: without it that call fails, nothing else does)
+    if (scratch_address(device, &c->scratch) != hipSuccess) c->scratch = nullptr;
     c->n_cu = prop.multiProcessorCount;
     int wall = 0;
     if (hipDeviceGetAttribute(&wall, hipDeviceAttributeWallClockRate, device) != hipSuccess || wall <= 0)
@@ -329,6 +365,7 @@ struct JobSeg {
 // transmitter and the options.
 struct TraceJob {
     std::vector<JobSeg> segs;
+    JobSeg *one = nullptr;     // set: the launch's single segment, held by the caller (no heap)
     rt_trace_opts opts{};
     int n_rays = 0;
     int tail = 0;              // launch-wide hand-off threshold actually used (0: none)
@@ -340,6 +377,8 @@ struct TraceJob {
     int32_t *tcount = nullptr;
     double *traj = nullptr;
     int64_t per_ray = 0;
+    size_t n_segs() const { return one ? 1 : segs.size(); }
+    const JobSeg &seg(size_t k) const { return one ? *one : segs[k]; }
 };
 
 static_assert(sizeof(TraceParams<float>) <= sizeof(TraceParams<double>),
@@ -380,13 +419,13 @@ size_t fan_values(const rt_fan &f) { return size_t(f.n_elev) + f.n_az + f.n_freq
 Layout job_layout(const TraceJob &j)
 {
     size_t nf = 0;
-    for (const JobSeg &s : j.segs) nf += fan_values(s.fan);
+    for (size_t k = 0; k < j.n_segs(); ++k) nf += fan_values(j.seg(k).fan);
     Layout L;
     L.seg = align_up(nf * 8, 256);
-    L.par = L.seg + align_up(j.segs.size() * sizeof(Segment), 256);
+    L.par = L.seg + align_up(j.n_segs() * sizeof(Segment), 256);
     L.cnt = L.par + align_up(sizeof(TraceParams<double>), 256);
     L.steps = L.cnt + align_up(sizeof(Counters), 64);
-    L.hand = L.steps + align_up(j.segs.size() * 8, 256);
+    L.hand = L.steps + align_up(j.n_segs() * 8, 256);
     L.host_bytes = L.hand;
     L.rec = L.hand + align_up(size_t(j.tail) * sizeof(Handoff), 256);
     L.ids = L.rec + align_up(size_t(j.n_rays) * sizeof(RayRec), 256);
@@ -466,7 +505,7 @@ void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
 {
     job.opts = opts;
     int64_t n64 = 0;
-    for (const JobSeg &s : job.segs) n64 += s.n_rays;
+    for (size_t k = 0; k < job.n_segs(); ++k) n64 += job.seg(k).n_rays;
     job.n_rays = int(n64);
     job.occ = opts.waves_per_simd == 0 ? 1 : opts.waves_per_simd;
     const int tail = opts.tail_threshold == 0 ? ctx->n_cu * 16 : opts.tail_threshold;
@@ -502,14 +541,14 @@ template <typename T>
 void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char *dev, int n_producers,
                  int n_promote, int64_t wall_khz)
 {
-    const JobSeg &s0 = job.segs[0];
+    const JobSeg &s0 = job.seg(0);
     const rt_grid_geom &gq = s0.grid->geom;
     const rt_fan *fan = &s0.fan;
     const rt_trace_opts *opts = &job.opts;
     fill_grid_dev<T>(s0.grid, P.g);
     const double la = fan->tx_lat_deg * kDeg2Rad, lo = fan->tx_lon_deg * kDeg2Rad;
     P.seg = reinterpret_cast<const Segment *>(dev + lay.seg);
-    P.n_seg = int32_t(job.segs.size());
+    P.n_seg = int32_t(job.n_segs());
     P.n_rays = job.n_rays;
     P.tx_lon = lo;
     P.up[0] = std::cos(la) * std::cos(lo); P.up[1] = std::cos(la) * std::sin(lo); P.up[2] = std::sin(la);
@@ -580,8 +619,8 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     size_t off = 0;
     int start = 0;
     const bool mixed = job.opts.precision == RT_MIXED;
-    for (size_t k = 0; k < job.segs.size(); ++k) {
-        const JobSeg &js = job.segs[k];
+    for (size_t k = 0; k < job.n_segs(); ++k) {
+        const JobSeg &js = job.seg(k);
         const rt_fan &f = js.fan;
         double *fe = h_fan + off;
         std::copy(f.elev_deg, f.elev_deg + f.n_elev, fe);
@@ -607,7 +646,7 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         start += js.n_rays;
         off += fan_values(f);
     }
-    const bool cr = job.segs[0].grid->geom.interp == RT_INTERP_CR;
+    const bool cr = job.seg(0).grid->geom.interp == RT_INTERP_CR;
     const int occ = job.occ;
     const void *kt;
     const void *kl;
@@ -638,7 +677,7 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     // requests keep every resident wave for throughput.
     const int max_waves = resident_waves<double>(ctx, kt);
     const int n_promote = job.promote > 0 && max_waves > 2 * job.promote ? job.promote : 0;
-    const int cap = n_promote > 0 && job.segs.size() == 1 ? std::min(max_waves, 4 * ctx->n_cu) : max_waves;
+    const int cap = n_promote > 0 && job.n_segs() == 1 ? std::min(max_waves, 4 * ctx->n_cu) : max_waves;
     const int producers = std::max(1, std::min((job.n_rays + 63) / 64, cap - n_promote));
     const int waves = producers + n_promote;
     Counters hc{};
@@ -702,8 +741,8 @@ void job_counters(const TraceJob &job, const char *host, Counters &c, std::vecto
     const Layout lay = job_layout(job);
     const char *rb = readback ? readback : host + lay.cnt;
     std::memcpy(&c, rb, sizeof(c));
-    steps.resize(job.segs.size());
-    for (size_t k = 0; k < job.segs.size(); ++k) {
+    steps.resize(job.n_segs());
+    for (size_t k = 0; k < job.n_segs(); ++k) {
         unsigned long long v;
         std::memcpy(&v, rb + (lay.steps - lay.cnt) + 8 * k, 8);
         steps[k] = int64_t(v);
@@ -724,6 +763,43 @@ rt_status ensure_pinned(rt_ctx *ctx, size_t bytes)
 
 }  // namespace
 
+namespace {
+
+// Results of a finished single-request launch: device time per phase and
+// the counters (ray-steps, launch errors).
+rt_status trace_results(rt_ctx *ctx, const TraceJob &job, const char *host, rt_results *res,
+                        int64_t &seg_steps)
+{
+    float ms = 0.f, ms_trace = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms_trace, ctx->ev0, ctx->evm));
+    const Layout lay = job_layout(job);
+    Counters hc;
+    std::memcpy(&hc, host + lay.cnt, sizeof(hc));
+    unsigned long long v;
+    std::memcpy(&v, host + lay.steps, 8);
+    seg_steps = int64_t(v);
+    res->total_steps = seg_steps;
+    res->kernel_ms = ms;
+    res->trace_ms = ms_trace;
+    res->tail_ms = ms - ms_trace;
+    res->steps_one_lane = int64_t(hc.phase_steps[0]);
+    res->steps_promoted = int64_t(hc.phase_steps[1]);
+    res->steps_rows = int64_t(hc.phase_steps[2]);
+    rt_status st = launch_error(ctx, hc);
+    if (st != RT_OK) return st;
+    return hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+}
+
+void clear_results(rt_results *res)
+{
+    res->total_steps = 0;
+    res->kernel_ms = res->trace_ms = res->tail_ms = 0.0;
+    res->steps_one_lane = res->steps_promoted = res->steps_rows = 0;
+}
+
+}  // namespace
+
 extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
                               const rt_trace_opts *opts, rt_results *res)
 {
@@ -734,9 +810,7 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
     rt_status st = validate_request(ctx, grid, fan, opts, job.segs[0]);
     if (st != RT_OK) return st;
     finish_job(ctx, job, *opts);
-    res->total_steps = 0;
-    res->kernel_ms = res->trace_ms = res->tail_ms = 0.0;
-    res->steps_one_lane = res->steps_promoted = res->steps_rows = 0;
+    clear_results(res);
     if (job.n_rays == 0) return RT_OK;
     const int64_t n64 = job.n_rays;
     if (opts->traj_stride > 0 && (!res->traj || opts->traj_capacity < n64))
@@ -790,22 +864,51 @@ extern "C" rt_status rt_trace(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fa
                                             hipMemcpyDeviceToHost, ctx->stream));
     }
     HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
-    float ms = 0.f;
-    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    float ms_trace = 0.f;
-    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms_trace, ctx->ev0, ctx->evm));
-    Counters hc;
-    std::vector<int64_t> steps;
-    job_counters(job, pinned, hc, steps);
-    res->total_steps = steps[0];
-    res->kernel_ms = ms;
-    res->trace_ms = ms_trace;
-    res->tail_ms = ms - ms_trace;
-    res->steps_one_lane = int64_t(hc.phase_steps[0]);
-    res->steps_promoted = int64_t(hc.phase_steps[1]);
-    res->steps_rows = int64_t(hc.phase_steps[2]);
-    if ((st = launch_error(ctx, hc)) != RT_OK) return st;
-    return hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
+    int64_t steps = 0;
+    return trace_results(ctx, job, pinned, res, steps);
+}
+
+extern "C" rt_status rt_trace_noalloc(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
+                                      const rt_trace_opts *opts, rt_results *res)
+{
+    if (!ctx) return RT_E_INVALID;
+    if (!res || !fan || !opts) return fail(ctx, RT_E_INVALID, "NULL argument");
+    if (opts->results_mem != RT_MEM_DEVICE)
+        return fail(ctx, RT_E_INVALID, "rt_trace_noalloc writes device results only (results_mem)");
+    if (opts->traj_stride != 0) return fail(ctx, RT_E_INVALID, "rt_trace_noalloc records no trajectories");
+    if (int64_t(fan->n_elev) + fan->n_az + fan->n_freq > RT_NOALLOC_MAX_AXIS)
+        return fail(ctx, RT_E_INVALID, "fan axes exceed RT_NOALLOC_MAX_AXIS values");
+    int64_t n64 = 0;
+    if (rt_fan_count(fan, &n64) == RT_OK && n64 > RT_NOALLOC_MAX_RAYS)
+        return fail(ctx, RT_E_INVALID, "fan exceeds RT_NOALLOC_MAX_RAYS rays");
+    // One segment, held in place (no heap): JobSeg and the options by value.
+    TraceJob job;
+    JobSeg seg;
+    rt_status st = validate_request(ctx, grid, fan, opts, seg);
+    if (st != RT_OK) return st;
+    job.one = &seg;
+    finish_job(ctx, job, *opts);
+    clear_results(res);
+    if (job.n_rays == 0) return RT_OK;
+    const Layout lay = job_layout(job);
+    if (lay.dev_bytes > size_t(RT_NOALLOC_SCRATCH_BYTES) || lay.host_bytes > sizeof(ctx->noalloc_host))
+        return fail(ctx, RT_E_INVALID, "launch exceeds the no-allocation scratch region");
+    if (!ctx->scratch) return fail(ctx, RT_E_DEVICE, "no scratch region on this device");
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    double *dbl[7] = {res->group_km, res->phase_km, res->range_km, res->az_dev_deg,
+                      res->apogee_km, res->land_lat_deg, res->land_lon_deg};
+    for (int k = 0; k < 7; ++k) seg.out[k] = dbl[k];
+    seg.status = res->status;
+    seg.nsteps = res->n_steps;
+    // The staging is pageable host memory: the upload and the counter
+    // read-back are ordered on the stream, and the call synchronizes before
+    // it reads the counters or returns.
+    if ((st = enqueue_job(ctx, ctx->stream, job, ctx->scratch, ctx->noalloc_host, ctx->ev0, ctx->ev1,
+                          nullptr, ctx->evm)) != RT_OK)
+        return st;
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    int64_t steps = 0;
+    return trace_results(ctx, job, ctx->noalloc_host, res, steps);
 }
 
 extern "C" rt_status rt_ionogram(rt_ctx *ctx, const rt_fan *fan, const rt_results *res,

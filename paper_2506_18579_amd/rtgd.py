@@ -23,6 +23,10 @@ RT_INTERP_GD, RT_INTERP_CR = 0, 1
 RT_MODE_O, RT_MODE_X = 1, 2
 RT_FP64, RT_MIXED = 0, 1
 RT_MEM_HOST, RT_MEM_DEVICE = 0, 1
+# limits of rt_trace_noalloc (include/rtgd.h)
+RT_NOALLOC_SCRATCH_BYTES = 40 << 20
+RT_NOALLOC_MAX_RAYS = 131072
+RT_NOALLOC_MAX_AXIS = 4096
 GROUND, ESCAPE, MAX_PATH, NUMERIC = 0, 1, 2, 3
 STATUS_NAMES = {RT_OK: "RT_OK", RT_W_TRAJ_TRUNCATED: "RT_W_TRAJ_TRUNCATED",
                 RT_E_INVALID: "RT_E_INVALID", RT_E_NOMEM: "RT_E_NOMEM",
@@ -134,6 +138,8 @@ def lib():
     L.rt_trace.argtypes = [vp, vp, ctypes.POINTER(Fan), ctypes.POINTER(TraceOpts),
                            ctypes.POINTER(Results)]
     L.rt_trace.restype = ctypes.c_int32
+    L.rt_trace_noalloc.argtypes = L.rt_trace.argtypes
+    L.rt_trace_noalloc.restype = ctypes.c_int32
     L.rt_fan_count.argtypes = [ctypes.POINTER(Fan), ctypes.POINTER(ctypes.c_int64)]
     L.rt_fan_count.restype = ctypes.c_int32
     L.rt_check_geom.argtypes = [ctypes.POINTER(GridGeom)]
@@ -315,7 +321,8 @@ def make_opts(step_km=1.0, max_group_km=4000.0, exit_h_km=0.0, precision="fp64",
 
 def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
           precision="fp64", traj_stride=0, traj_per_ray=0, device_results=False, out=None,
-          tail_threshold=0, waves_per_simd=0, ray_order=0, promote_waves=0, promote_age=0):
+          tail_threshold=0, waves_per_simd=0, ray_order=0, promote_waves=0, promote_age=0,
+          _entry="rt_trace"):
     """Trace every ray of `fan` (synth.Fan) through `grid`.
 
     Returns a dict of per-ray arrays (numpy on the host, or torch tensors on
@@ -359,8 +366,8 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
     if traj_stride > 0:
         r.traj = ptr(out["traj"], _DP)
         r.traj_count = ptr(out["traj_count"], _IP)
-    st = lib().rt_trace(ctx.h, grid.h, ctypes.byref(fa.s), ctypes.byref(o), ctypes.byref(r))
-    ctx.check(st, "rt_trace")
+    st = getattr(lib(), _entry)(ctx.h, grid.h, ctypes.byref(fa.s), ctypes.byref(o), ctypes.byref(r))
+    ctx.check(st, _entry)
     res = dict(out)
     res["total_steps"] = int(r.total_steps)
     res["kernel_ms"] = float(r.kernel_ms)
@@ -369,6 +376,17 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
     res["tail_ms"] = float(r.tail_ms)
     res["truncated"] = st == RT_W_TRAJ_TRUNCATED
     return res
+
+
+def trace_noalloc(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
+                  precision="fp64", out=None, tail_threshold=0, waves_per_simd=0, ray_order=0,
+                  promote_waves=0, promote_age=0):
+    """rt_trace_noalloc: trace() with device results and no trajectories,
+    every launch buffer taken from the library's per-device scratch region
+    (the library allocates nothing; `out`, if given, is reused)."""
+    return trace(ctx, grid, fan, step_km, max_group_km, exit_h_km, precision, 0, 0, True, out,
+                 tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age,
+                 _entry="rt_trace_noalloc")
 
 
 def trace_raw(ctx: Context, grid: Grid, fan_struct: Fan, opts: TraceOpts, res: Results) -> int:

@@ -172,3 +172,13 @@ def test_tune_cache_rejects_malformed_lines(rt, tmp_path, bad):
         rt.tune_cache_load(str(p))
     with pytest.raises(rt.RTError):
         rt.tune_cache_load(str(tmp_path / "missing.txt"))
+
+
+def test_noalloc_limits_match_header(rt):
+    """The binding's copies of the rt_trace_noalloc limits are the header's."""
+    src = open(os.path.join(ROOT, "include", "rtgd.h")).read()
+    for name in ("RT_NOALLOC_SCRATCH_BYTES", "RT_NOALLOC_MAX_RAYS", "RT_NOALLOC_MAX_AXIS"):
+        m = re.search(r"#define " + name + r" \(?([0-9]+)(?: << ([0-9]+))?\)?", src)
+        assert m, name
+        val = int(m.group(1)) << int(m.group(2) or 0)
+        assert getattr(rt, name) == val, name
