@@ -47,7 +47,8 @@ TRAFFIC_SOURCES = {
 
 
 # launch settings the autotuner chooses (results do not depend on them)
-TUNED_KNOBS = ("tail_threshold", "waves_per_simd", "ray_order", "promote_waves", "promote_age")
+TUNED_KNOBS = ("tail_threshold", "waves_per_simd", "ray_order", "promote_waves", "promote_age",
+               "cu_layout")
 
 
 def measured_traffic():

@@ -157,6 +157,16 @@ typedef struct {
     int32_t promote_age;    /* steps after which any ray may be promoted;
                                0 = default and -1: never (trapped and
                                grazing rays only)                          */
+    int32_t cu_layout;      /* scheduling knob, results unchanged: how the
+                               one-lane kernel's waves are grouped when
+                               promotion waves run.  1: one wave per
+                               work-group; 2: four waves per work-group and
+                               one work-group per CU (an LDS reservation
+                               keeps others off the CU), so the promotion
+                               waves, the launch's last work-groups, have
+                               CUs to themselves; 0 = default: 2 for a
+                               single-request launch (rt_trace, a plan, a
+                               server batch of one), else 1                */
 } rt_trace_opts;
 
 /* Per-ray outputs, arrays of N_r = rt_fan_count() elements, owned by the
@@ -362,16 +372,16 @@ void rt_plan_destroy(rt_plan *plan);
 
 /* ------------------------------------------------------------------------
  * Autotuner.  The launch settings that change speed but not results are
- * tail_threshold, waves_per_simd, ray_order, promote_waves and promote_age
- * (see rt_trace_opts).  rt_autotune traces the given fan for every
+ * tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age and
+ * cu_layout (see rt_trace_opts).  rt_autotune traces the given fan for every
  * candidate setting (tail_threshold in {-2, -1, 8 and 16 rays per CU} x
  * waves_per_simd in {1, 2} x ray_order in {index, strided}; then, on top of
  * the fastest of those unless it is the in-wave switch, promote_waves in
- * {16, 32, 64} with promote_age -1; the first stage runs without
- * promotion; one untimed run, then the median device time of three), keeps
- * the fastest if it beats the library defaults by at least 2 % (else the
- * defaults, all five fields 0) and writes base with those five fields
- * replaced to *tuned.  Choices are cached in the process under a key made of the
+ * {16, 32, 64} with promote_age -1, each with cu_layout 2 and 1; the first
+ * stage runs without promotion; one untimed run, then the median device
+ * time of three), keeps the fastest if it beats the library defaults by at
+ * least 2 % (else the defaults, all six fields 0) and writes base with
+ * those six fields replaced to *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on
  * or off and the ray count rounded to a power of two; a cached key is
  * answered without tracing.  Results of the trial traces are discarded

@@ -32,6 +32,7 @@ struct rt_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int n_cu = 0;
+    int lds_lock = 0;           // LDS bytes per work-group that leave room for one per CU (0: none)
     int64_t wall_khz = 0;       // rate of the device's constant wall clock
     // workspace (grow-only)
     void *ws = nullptr;
@@ -221,6 +222,22 @@ rt_status rt_ctx_create(int32_t device, void *stream, rt_ctx **out)
     // needs it: without it that call fails, nothing else does)
     if (scratch_address(device, &c->scratch) != hipSuccess) c->scratch = nullptr;
     c->n_cu = prop.multiProcessorCount;
+    // one work-group per CU for the grouped one-lane kernel: reserve more
+    // than half of a CU's LDS per work-group (the kernels use none)
+    {
+        const size_t per_cu = prop.maxSharedMemoryPerMultiProcessor;
+        const size_t lock = per_cu / 2 + 4096;
+        if (per_cu > 0 && lock <= prop.sharedMemPerBlock &&
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<double, 0>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess &&
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<double, 1>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess &&
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<float, 0>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess &&
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<float, 1>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess)
+            c->lds_lock = int(lock);
+    }
     int wall = 0;
     if (hipDeviceGetAttribute(&wall, hipDeviceAttributeWallClockRate, device) != hipSuccess || wall <= 0)
         wall = 100000;          // 100 MHz, the usual rate
@@ -462,6 +479,8 @@ rt_status validate_request(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
         return fail(ctx, RT_E_INVALID, "promote_waves must be in [-1, 64]");
     if (opts->promote_age < -1)
         return fail(ctx, RT_E_INVALID, "promote_age must be >= -1");
+    if (opts->cu_layout < 0 || opts->cu_layout > 2)
+        return fail(ctx, RT_E_INVALID, "cu_layout must be 0, 1 or 2");
     if (opts->traj_stride < 0 || opts->traj_capacity < 0)
         return fail(ctx, RT_E_INVALID, "negative trajectory option");
     if (!(fan->tx_h_km >= 0.0) || !(fan->tx_h_km < gq.h0_km))
@@ -533,7 +552,7 @@ bool compatible(const JobSeg &a, const rt_trace_opts &oa, const JobSeg &b, const
            oa.exit_h_km == ob.exit_h_km && oa.precision == ob.precision &&
            oa.tail_threshold == ob.tail_threshold && oa.waves_per_simd == ob.waves_per_simd &&
            oa.ray_order == ob.ray_order && oa.promote_waves == ob.promote_waves &&
-           oa.promote_age == ob.promote_age &&
+           oa.promote_age == ob.promote_age && oa.cu_layout == ob.cu_layout &&
            oa.traj_stride == 0 && ob.traj_stride == 0;
 }
 
@@ -649,6 +668,7 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     const bool cr = job.seg(0).grid->geom.interp == RT_INTERP_CR;
     const int occ = job.occ;
     const void *kt;
+    const void *ktg;  // the one-lane kernel grouped four waves per work-group
     const void *kl;
     const void *ks;   // starting states
     const void *kf;   // outputs
@@ -657,6 +677,7 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         kf = (const void *)k_finish<float>;
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<float, 1> : (const void *)k_trace_w2<float, 0>)
                       : (cr ? (const void *)k_trace<float, 1> : (const void *)k_trace<float, 0>);
+        ktg = cr ? (const void *)k_trace_g<float, 1> : (const void *)k_trace_g<float, 0>;
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<float, 1> : (const void *)k_tail_w2<float, 0>)
                       : (cr ? (const void *)k_tail<float, 1> : (const void *)k_tail<float, 0>);
     } else {
@@ -664,6 +685,7 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         kf = (const void *)k_finish<double>;
         kt = occ == 2 ? (cr ? (const void *)k_trace_w2<double, 1> : (const void *)k_trace_w2<double, 0>)
                       : (cr ? (const void *)k_trace<double, 1> : (const void *)k_trace<double, 0>);
+        ktg = cr ? (const void *)k_trace_g<double, 1> : (const void *)k_trace_g<double, 0>;
         kl = occ == 2 ? (cr ? (const void *)k_tail_w2<double, 1> : (const void *)k_tail_w2<double, 0>)
                       : (cr ? (const void *)k_tail<double, 1> : (const void *)k_tail<double, 0>);
     }
@@ -673,12 +695,25 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     // With promotion on, a single-request launch holds at most one wave per
     // SIMD: a promotion wave runs the launch's longest rays, and beside a
     // one-lane wave on the same SIMD it would issue at half rate (the FP32
-    // kernels fit two waves per SIMD).  Launches that batch several server
-    // requests keep every resident wave for throughput.
+    // kernels fit two waves per SIMD).  The grouped layout goes further:
+    // four-wave work-groups, one per CU, so that the promotion waves share
+    // no CU (its memory pipeline and caches) with one-lane waves.  Launches
+    // that batch several server requests keep every resident wave for
+    // throughput.
     const int max_waves = resident_waves<double>(ctx, kt);
-    const int n_promote = job.promote > 0 && max_waves > 2 * job.promote ? job.promote : 0;
-    const int cap = n_promote > 0 && job.n_segs() == 1 ? std::min(max_waves, 4 * ctx->n_cu) : max_waves;
-    const int producers = std::max(1, std::min((job.n_rays + 63) / 64, cap - n_promote));
+    int n_promote = job.promote > 0 && max_waves > 2 * job.promote ? job.promote : 0;
+    const bool grouped = n_promote > 0 && ctx->lds_lock > 0 &&
+                         (job.opts.cu_layout == 2 || (job.opts.cu_layout == 0 && job.n_segs() == 1));
+    int producers;
+    if (grouped) {
+        n_promote = (n_promote + 3) / 4 * 4;
+        const int cap = 4 * ctx->n_cu;
+        producers = std::max(4, std::min((job.n_rays + 63) / 64, cap - n_promote));
+        producers = (producers + 3) / 4 * 4;     // whole work-groups: cap - n_promote is a multiple of 4
+    } else {
+        const int cap = n_promote > 0 && job.n_segs() == 1 ? std::min(max_waves, 4 * ctx->n_cu) : max_waves;
+        producers = std::max(1, std::min((job.n_rays + 63) / 64, cap - n_promote));
+    }
     const int waves = producers + n_promote;
     Counters hc{};
     hc.live = job.n_rays;
@@ -704,7 +739,10 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     const dim3 per_ray((job.n_rays + 63) / 64);
     if (ev0) HIP_OR_FAIL(ctx, hipEventRecord(ev0, stream));
     HIP_OR_FAIL(ctx, hipLaunchKernel(ks, per_ray, dim3(64), args, 0, stream));
-    HIP_OR_FAIL(ctx, hipLaunchKernel(kt, dim3(waves), dim3(64), args, 0, stream));
+    if (grouped)
+        HIP_OR_FAIL(ctx, hipLaunchKernel(ktg, dim3(waves / 4), dim3(256), args, size_t(ctx->lds_lock), stream));
+    else
+        HIP_OR_FAIL(ctx, hipLaunchKernel(kt, dim3(waves), dim3(64), args, 0, stream));
     if (evm) HIP_OR_FAIL(ctx, hipEventRecord(evm, stream));
     if (job.tail > 0)
         HIP_OR_FAIL(ctx, hipLaunchKernel(kl, dim3((job.tail + 3) / 4), dim3(64), args, 0, stream));
@@ -1478,7 +1516,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int32_t tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age;
+    int32_t tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age, cu_layout;
 };
 
 std::mutex g_tune_mu;
@@ -1515,6 +1553,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
             tuned->ray_order = it->second.ray_order;
             tuned->promote_waves = it->second.promote_waves;
             tuned->promote_age = it->second.promote_age;
+            tuned->cu_layout = it->second.cu_layout;
             inf.from_cache = 1;
             if (info) *info = inf;
             return RT_OK;
@@ -1552,13 +1591,14 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
         return RT_OK;
     };
     double best = 1e300;
-    TuneVal bv{0, 0, 0, 0, 0};
+    TuneVal bv{0, 0, 0, 0, 0, 0};
     rt_trace_opts o = *base;
     o.tail_threshold = 0;
     o.waves_per_simd = 0;
     o.ray_order = 0;
     o.promote_waves = 0;
     o.promote_age = 0;
+    o.cu_layout = 0;
     st = time_opts(o, inf.default_ms);
     o.promote_waves = -1;     // the first stage runs without promotion
     for (int oc : occs) {
@@ -1571,26 +1611,33 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
                 double ms = 0;
                 st = time_opts(o, ms);
                 ++inf.n_candidates;
-                if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od, -1, 0}; }
+                if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od, -1, 0, 0}; }
             }
         }
     }
-    // then promotion on top of the best of those (not with the in-wave switch)
+    // then promotion on top of the best of those (not with the in-wave
+    // switch), in both work-group layouts
     const int promos[3][2] = {{16, -1}, {32, -1}, {64, -1}};
+    const int layouts[2] = {2, 1};
     if (bv.tail_threshold != -2) {
+        const TuneVal base_v = bv;
         for (const auto &pr : promos) {
-            if (st != RT_OK) break;
-            o.tail_threshold = bv.tail_threshold;
-            o.waves_per_simd = bv.waves_per_simd;
-            o.ray_order = bv.ray_order;
-            o.promote_waves = pr[0];
-            o.promote_age = pr[1];
-            double ms = 0;
-            st = time_opts(o, ms);
-            ++inf.n_candidates;
-            if (st == RT_OK && ms < best) {
-                best = ms;
-                bv = TuneVal{bv.tail_threshold, bv.waves_per_simd, bv.ray_order, pr[0], pr[1]};
+            for (int lay : layouts) {
+                if (st != RT_OK) break;
+                o.tail_threshold = base_v.tail_threshold;
+                o.waves_per_simd = base_v.waves_per_simd;
+                o.ray_order = base_v.ray_order;
+                o.promote_waves = pr[0];
+                o.promote_age = pr[1];
+                o.cu_layout = lay;
+                double ms = 0;
+                st = time_opts(o, ms);
+                ++inf.n_candidates;
+                if (st == RT_OK && ms < best) {
+                    best = ms;
+                    bv = TuneVal{base_v.tail_threshold, base_v.waves_per_simd, base_v.ray_order, pr[0], pr[1],
+                                 lay};
+                }
             }
         }
     }
@@ -1599,7 +1646,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     // keep the library defaults unless a candidate is clearly faster
     if (!(best < 0.98 * inf.default_ms)) {
         best = inf.default_ms;
-        bv = TuneVal{0, 0, 0, 0, 0};
+        bv = TuneVal{0, 0, 0, 0, 0, 0};
     }
     inf.best_ms = best;
     tuned->tail_threshold = bv.tail_threshold;
@@ -1607,6 +1654,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     tuned->ray_order = bv.ray_order;
     tuned->promote_waves = bv.promote_waves;
     tuned->promote_age = bv.promote_age;
+    tuned->cu_layout = bv.cu_layout;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = bv;
@@ -1622,13 +1670,13 @@ extern "C" rt_status rt_tune_cache_save(const char *path)
     if (!f) return RT_E_INVALID;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     f << "# n_cu n_lat n_lon n_h interp precision field log2_rays -> tail_threshold waves_per_simd "
-         "ray_order promote_waves promote_age\n";
+         "ray_order promote_waves promote_age cu_layout\n";
     for (const auto &kv : g_tune_cache) {
         const TuneKey &k = kv.first;
         f << k.n_cu << ' ' << k.n_lat << ' ' << k.n_lon << ' ' << k.n_h << ' ' << k.interp << ' '
           << k.precision << ' ' << k.field << ' ' << k.log2_rays << ' ' << kv.second.tail_threshold << ' '
           << kv.second.waves_per_simd << ' ' << kv.second.ray_order << ' ' << kv.second.promote_waves << ' '
-          << kv.second.promote_age << '\n';
+          << kv.second.promote_age << ' ' << kv.second.cu_layout << '\n';
     }
     return f.good() ? RT_OK : RT_E_INVALID;
 }
@@ -1647,13 +1695,13 @@ extern "C" rt_status rt_tune_cache_load(const char *path)
         TuneVal v{};
         if (!(ss >> k.n_cu >> k.n_lat >> k.n_lon >> k.n_h >> k.interp >> k.precision >> k.field >>
               k.log2_rays >> v.tail_threshold >> v.waves_per_simd >> v.ray_order >> v.promote_waves >>
-              v.promote_age))
+              v.promote_age >> v.cu_layout))
             return RT_E_INVALID;
         std::string rest;
         if (ss >> rest) return RT_E_INVALID;
         if (v.waves_per_simd < 0 || v.waves_per_simd > 2 || v.tail_threshold > (1 << 24) ||
             v.tail_threshold < -2 || v.ray_order < 0 || v.ray_order > 2 || v.promote_waves < -1 ||
-            v.promote_waves > kMaxPromoteWaves || v.promote_age < -1)
+            v.promote_waves > kMaxPromoteWaves || v.promote_age < -1 || v.cu_layout < 0 || v.cu_layout > 2)
             return RT_E_INVALID;
         loaded[k] = v;
     }

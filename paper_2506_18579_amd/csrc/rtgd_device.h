@@ -213,6 +213,16 @@ __device__ __forceinline__ double dpp(double v)
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
+// Broadcast of lane N of each 16-lane row to the whole row (row_newbcast);
+// gfx950 moves a 64-bit value this way in one instruction.
+template <int N>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    const long long x = __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + N, 0xF, 0xF, true);
+    return __longlong_as_double(x);
+}
+template <int N>
+__device__ __forceinline__ float row_bcast(float v) { return dpp<0x150 + N>(v); }
 constexpr int kQuadXor1 = 0xB1;          // quad_perm(1, 0, 3, 2): lane ^ 1
 constexpr int kQuadXor2 = 0x4E;          // quad_perm(2, 3, 0, 1): lane ^ 2
 constexpr int kRowMirror = 0x140;        // lane i <- lane 15 - i within 16
@@ -364,13 +374,14 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
         eval_piece<T, IP>(sc.pb, T(so_), wo, dwo);
         eval_piece<T, IP>(sc.pa, T(sl_), wl, dwl);
         // height weights: lane b of each quad evaluates node b's piece (the
-        // same piece as its longitude weight), the quad shares them
+        // same piece as its longitude weight); lanes 0..3 of the row hold
+        // pieces 0..3, which the row broadcasts
         eval_piece<T, IP>(sc.pb, T(sh_), w1, dw1);
         T wh[4], dwh[4];
-        wh[0] = dpp<0x00>(w1); dwh[0] = dpp<0x00>(dw1);
-        wh[1] = dpp<0x55>(w1); dwh[1] = dpp<0x55>(dw1);
-        wh[2] = dpp<0xAA>(w1); dwh[2] = dpp<0xAA>(dw1);
-        wh[3] = dpp<0xFF>(w1); dwh[3] = dpp<0xFF>(dw1);
+        wh[0] = row_bcast<0>(w1); dwh[0] = row_bcast<0>(dw1);
+        wh[1] = row_bcast<1>(w1); dwh[1] = row_bcast<1>(dw1);
+        wh[2] = row_bcast<2>(w1); dwh[2] = row_bcast<2>(dw1);
+        wh[3] = row_bcast<3>(w1); dwh[3] = row_bcast<3>(dw1);
         T uu[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) uu[c] = sc.u[0][0][c] - uref;
@@ -410,42 +421,41 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
 
 // Appleton-Hartree partial derivatives of mu^2 with respect to X,
 // a = Y_T^2 and b = Y_L^2 (independent), given X and u = 1 - X (formed by
-// the caller in FP64).  O mode from the factored D = 2(1-X) E,
-// E = 1 + 2b(1-X)/(S+a) (exact rearrangement, no cancellation as X -> 1);
-// X mode from D as printed.
+// the caller in FP64), for the O mode (sigma > 0) and the X mode in one
+// instruction stream, so that rays of both modes in one wave (or on the rows
+// of one wave) run no divergent branch.  Both modes are written as
+// mu^2 = 1 - X / E, an exact rearrangement of eq. appleton with
+// D = 2u - a + sigma S = 2u E, S = sqrt(a^2 + 4 b u^2), T = S + a:
+//   O:  E = 1 + 2 b u / T   (S - a = 4 b u^2 / T: no cancellation as X -> 1)
+//   X:  E = 1 - T / (2 u)   (u >= Y > 0 where the X mode propagates)
+// With k = (E - 1) / u (O: 2b/T, X: -T/(2u^2)) and m = -sigma k / S:
+//   dE/dX = a m,  dE/da = u m,
+//   dE/db = O: 2u/T - 4 b u^3 / (S T^2),  X: -u / S,
+// and mu^2_X = -1/E + X E_X / E^2, mu^2_a = X E_a / E^2, mu^2_b = X E_b / E^2.
+// The mode-specific terms are selects: a candidate that is infinite for the
+// other mode (1/u where the O mode reflects) is never used.
 template <typename T>
 __device__ __forceinline__ void appleton_partials(T X, T u, T a, T b, int sigma, T &mX, T &ma, T &mb)
 {
-    T bu = b * u;
+    const bool o_mode = sigma > 0;
+    const T bu = b * u;
     const T S2 = fm(a, a, T(4) * bu * u);
     const T iS = rsqrt(S2);
     const T S = S2 * iS;
-    T Tt = S + a;
-    if (sigma > 0) {
-        T iT = rcp(Tt);
-        T E = fm(T(2) * bu, iT, T(1));
-        T iE = rcp(E);
-        // dE/dX = 2b (4bu^2/S - T)/T^2; with S^2 = a^2 + 4bu^2 the bracket is
-        // exactly -aT/S, so dE/dX = -2ab/(S T) (no cancellation when a << S)
-        T EX = T(-2) * a * b * iS * iT;
-        T Ea = T(-2) * bu * iS * iT;
-        T Eb = fm(T(-4) * bu * u * u * iS, iT * iT, T(2) * u * iT);
-        T XiE2 = X * iE * iE;
-        mX = fm(EX, XiE2, -iE);
-        ma = Ea * XiE2;
-        mb = Eb * XiE2;
-    } else {
-        T D = fm(T(2), u, -Tt);
-        T iD = rcp(D);
-        T N = T(2) * X * u;
-        T DX = fm(T(4) * bu, iS, T(-2));
-        T Da = -Tt * iS;
-        T Db = T(-2) * u * u * iS;
-        T iD2 = iD * iD;
-        mX = -fm(T(2) * fm(T(-2), X, T(1)), D, -(N * DX)) * iD2;
-        ma = N * Da * iD2;
-        mb = N * Db * iD2;
-    }
+    const T Tt = S + a;
+    const T iT = rcp(Tt);
+    const T iu = rcp(u);
+    const T k = o_mode ? T(2) * b * iT : T(-0.5) * Tt * (iu * iu);
+    const T E = fm(k, u, T(1));
+    const T iE = rcp(E);
+    const T m = (o_mode ? -k : k) * iS;
+    const T EX = a * m;
+    const T Ea = u * m;
+    const T Eb = o_mode ? fm(T(-4) * bu * u * u * iS, iT * iT, T(2) * u * iT) : -(u * iS);
+    const T XiE2 = X * iE * iE;
+    mX = fm(EX, XiE2, -iE);
+    ma = Ea * XiE2;
+    mb = Eb * XiE2;
 }
 
 // dy/dP' of the 7-component state (r, th, ph, n_r, n_th, n_ph, P), given
@@ -477,11 +487,11 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
         Hn0 = nr; Hn1 = nt; Hn2 = np;
         Hr = T(0.5) * Xr; Hth = T(0.5) * Xth; Hph = T(0.5) * Xph;
     } else {
-        // axial dipole: Y_r = -2 Yc cos th, Y_th = -Yc sin th, Yc = Y0 (R/r)^3
+        // axial dipole: Y_r = -2 Yc cos th, Y_th = -Yc sin th, Yc = Y0 (R/r)^3;
+        // dY/dr = -3 Y / r (used below in closed form)
         const T q = T(g.R) * ir;
         const T Yc = T(rc.Y0) * (q * q * q);
         const T Y0 = T(-2) * Yc * ct, Y1 = -Yc * st;
-        const T Yr0 = T(-3) * Y0 * ir, Yr1 = T(-3) * Y1 * ir;   // dY/dr
         const T Yt0 = T(2) * Yc * st, Yt1 = -Yc * ct;           // dY/dth
         const T Y2 = fm(Y0, Y0, Y1 * Y1);
         const T Yn = fm(Y0, nr, Y1 * nt);
@@ -497,17 +507,18 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
         const T mb = mba - ma;       // d mu^2 / d b at fixed Y^2
         G = fm(X, mX, fm(Y2, mY2, fm(b, mb, -n2)));
         // dH/dn = n - mb/2 db/dn, db/dn = 2 Yn Y/n2 - 2 Yn^2 n / n2^2
+        // (Yn^2 / n2^2 = b / n2)
         const T c1 = mb * Yn * in2;
-        const T c2p = T(1) + mb * Yn * Yn * in2 * in2;
+        const T c2p = fm(mb * b, in2, T(1));
         Hn0 = fm(nr, c2p, -(c1 * Y0));
         Hn1 = fm(nt, c2p, -(c1 * Y1));
         Hn2 = np * c2p;
-        const T dY2r = T(2) * fm(Y0, Yr0, Y1 * Yr1);
+        // dH/dq = -1/2 (mX dX/dq + mY2 dY^2/dq + mb db/dq); with dY/dr = -3Y/r,
+        // dY^2/dr = -6 Y^2 / r and db/dr = -6 b / r
         const T dY2t = T(2) * fm(Y0, Yt0, Y1 * Yt1);
         const T tYn = T(2) * Yn * in2;
-        const T dbr = tYn * fm(Yr0, nr, Yr1 * nt);
         const T dbt = tYn * fm(Yt0, nr, Yt1 * nt);
-        Hr = T(-0.5) * fm(mX, Xr, fm(mY2, dY2r, mb * dbr));
+        Hr = fm(T(-0.5) * mX, Xr, T(3) * ir * fm(mY2, Y2, mb * b));
         Hth = T(-0.5) * fm(mX, Xth, fm(mY2, dY2t, mb * dbt));
         Hph = T(-0.5) * (mX * Xph);
     }

@@ -926,21 +926,38 @@ __global__ __launch_bounds__(64) void k_ionogram(const double *__restrict__ elev
     counts[t] = found;
 }
 
+// Waves [0, n_producers) of the launch run one lane per ray, the others are
+// promotion waves.  A work-group holds one wave (k_trace, k_trace_w2) or four
+// (k_trace_g), and a wave's index is its place in the launch.
+template <typename T, int IP>
+__device__ __forceinline__ void trace_entry(const TraceParams<T> &P, const TraceParams<T> *Pp)
+{
+    const int wave = int(blockIdx.x) * int(blockDim.x >> 6) + int(threadIdx.x >> 6);
+    if (wave >= P.n_producers) promote_body<T, IP>(P, Pp);
+    else trace_body<T, IP>(P, Pp);
+}
+
 // Launch wrappers.  The *_w2 variants ask the compiler to fit two waves per
 // SIMD (at most 256 VGPRs, spilling if needed); the plain ones let it use
-// the whole register file (one wave per SIMD for the FP64 path).
+// the whole register file (one wave per SIMD for the FP64 path).  k_trace_g
+// runs four waves per work-group and is launched with an LDS reservation
+// above half of a CU's LDS, so that each CU holds exactly one work-group:
+// the promotion waves (the last work-groups) then have CUs to themselves.
 template <typename T, int IP>
 __global__ __launch_bounds__(64) void k_trace(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
 {
-    if (int(blockIdx.x) >= P.n_producers) promote_body<T, IP>(P, Pp);
-    else trace_body<T, IP>(P, Pp);
+    trace_entry<T, IP>(P, Pp);
 }
 template <typename T, int IP>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 void k_trace_w2(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
 {
-    if (int(blockIdx.x) >= P.n_producers) promote_body<T, IP>(P, Pp);
-    else trace_body<T, IP>(P, Pp);
+    trace_entry<T, IP>(P, Pp);
+}
+template <typename T, int IP>
+__global__ __launch_bounds__(256) void k_trace_g(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)
+{
+    trace_entry<T, IP>(P, Pp);
 }
 template <typename T, int IP>
 __global__ __launch_bounds__(64) void k_tail(const TraceParams<T> P, const TraceParams<T> *__restrict__ Pp)

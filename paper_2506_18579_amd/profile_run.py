@@ -26,6 +26,7 @@ def main():
     ap.add_argument("--ray-order", type=int, default=0)
     ap.add_argument("--promote-waves", type=int, default=0)
     ap.add_argument("--promote-age", type=int, default=0)
+    ap.add_argument("--cu-layout", type=int, default=0)
     a = ap.parse_args()
     import torch
     from paper_2506_18579_amd import rtgd, synth
@@ -51,9 +52,12 @@ def main():
         out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
                          exit_h_km=wl.exit_km, precision=a.precision, device_results=True, out=out,
                          tail_threshold=a.tail, waves_per_simd=a.waves_per_simd, ray_order=a.ray_order,
-                         promote_waves=a.promote_waves, promote_age=a.promote_age)
+                         promote_waves=a.promote_waves, promote_age=a.promote_age,
+                         cu_layout=a.cu_layout)
         print(json.dumps({"rep": i, "workload": wl.name, "precision": a.precision,
-                          "ray_steps": out["total_steps"], "kernel_ms": out["kernel_ms"]}),
+                          "ray_steps": out["total_steps"], "kernel_ms": out["kernel_ms"],
+                          "trace_ms": out["trace_ms"], "tail_ms": out["tail_ms"],
+                          "phase_steps": out["phase_steps"]}),
               flush=True)
     grid.close()
     ctx.close()

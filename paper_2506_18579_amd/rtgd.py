@@ -65,7 +65,8 @@ class TraceOpts(ctypes.Structure):
                 ("traj_stride", ctypes.c_int32), ("traj_capacity", ctypes.c_int64),
                 ("results_mem", ctypes.c_int32), ("tail_threshold", ctypes.c_int32),
                 ("waves_per_simd", ctypes.c_int32), ("ray_order", ctypes.c_int32),
-                ("promote_waves", ctypes.c_int32), ("promote_age", ctypes.c_int32)]
+                ("promote_waves", ctypes.c_int32), ("promote_age", ctypes.c_int32),
+                ("cu_layout", ctypes.c_int32)]
 
 
 class Results(ctypes.Structure):
@@ -306,7 +307,7 @@ class Grid:
 
 def make_opts(step_km=1.0, max_group_km=4000.0, exit_h_km=0.0, precision="fp64",
               tail_threshold=0, waves_per_simd=0, ray_order=0, promote_waves=0,
-              promote_age=0) -> TraceOpts:
+              promote_age=0, cu_layout=0) -> TraceOpts:
     o = TraceOpts()
     lib().rt_default_opts(ctypes.byref(o))
     o.step_km, o.max_group_km, o.exit_h_km = step_km, max_group_km, exit_h_km
@@ -316,13 +317,14 @@ def make_opts(step_km=1.0, max_group_km=4000.0, exit_h_km=0.0, precision="fp64",
     o.ray_order = ray_order
     o.promote_waves = promote_waves
     o.promote_age = promote_age
+    o.cu_layout = cu_layout
     return o
 
 
 def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
           precision="fp64", traj_stride=0, traj_per_ray=0, device_results=False, out=None,
           tail_threshold=0, waves_per_simd=0, ray_order=0, promote_waves=0, promote_age=0,
-          _entry="rt_trace"):
+          cu_layout=0, _entry="rt_trace"):
     """Trace every ray of `fan` (synth.Fan) through `grid`.
 
     Returns a dict of per-ray arrays (numpy on the host, or torch tensors on
@@ -337,7 +339,7 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
         raise RTError(st, "invalid fan")
     n = int(n.value)
     o = make_opts(step_km, max_group_km, exit_h_km, precision, tail_threshold, waves_per_simd,
-                  ray_order, promote_waves, promote_age)
+                  ray_order, promote_waves, promote_age, cu_layout)
     o.traj_stride = traj_stride
     o.traj_capacity = traj_per_ray * n if traj_stride > 0 else 0
     o.results_mem = RT_MEM_DEVICE if device_results else RT_MEM_HOST
@@ -380,12 +382,12 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
 
 def trace_noalloc(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
                   precision="fp64", out=None, tail_threshold=0, waves_per_simd=0, ray_order=0,
-                  promote_waves=0, promote_age=0):
+                  promote_waves=0, promote_age=0, cu_layout=0):
     """rt_trace_noalloc: trace() with device results and no trajectories,
     every launch buffer taken from the library's per-device scratch region
     (the library allocates nothing; `out`, if given, is reused)."""
     return trace(ctx, grid, fan, step_km, max_group_km, exit_h_km, precision, 0, 0, True, out,
-                 tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age,
+                 tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age, cu_layout,
                  _entry="rt_trace_noalloc")
 
 
@@ -511,7 +513,7 @@ class Server:
 def autotune(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=0.0,
              precision="fp64") -> dict:
     """rt_autotune: the fastest (tail_threshold, waves_per_simd, ray_order,
-    promote_waves, promote_age) for this fan, from the process cache or by
+    promote_waves, promote_age, cu_layout) for this fan, from the process cache or by
     timing every candidate."""
     fa = FanArgs(fan)
     base = make_opts(step_km, max_group_km, exit_h_km, precision)
@@ -521,7 +523,8 @@ def autotune(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, ex
                                 ctypes.byref(tuned), ctypes.byref(info)), "rt_autotune")
     return dict(tail_threshold=int(tuned.tail_threshold), waves_per_simd=int(tuned.waves_per_simd),
                 ray_order=int(tuned.ray_order), promote_waves=int(tuned.promote_waves),
-                promote_age=int(tuned.promote_age), best_ms=float(info.best_ms),
+                promote_age=int(tuned.promote_age), cu_layout=int(tuned.cu_layout),
+                best_ms=float(info.best_ms),
                 default_ms=float(info.default_ms), n_candidates=int(info.n_candidates),
                 from_cache=bool(info.from_cache))
 
@@ -546,7 +549,7 @@ class Plan:
 
     def __init__(self, ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0,
                  exit_h_km=0.0, precision="fp64", tail_threshold=0, waves_per_simd=0, ray_order=0,
-                 promote_waves=0, promote_age=0):
+                 promote_waves=0, promote_age=0, cu_layout=0):
         import torch
         self.ctx, self.grid = ctx, grid
         n = fan_count(fan)
@@ -559,7 +562,7 @@ class Plan:
         for k in OUT_INT:
             setattr(r, k, ctypes.cast(ctypes.c_void_p(self.out[k].data_ptr()), _IP))
         o = make_opts(step_km, max_group_km, exit_h_km, precision, tail_threshold, waves_per_simd,
-                      ray_order, promote_waves, promote_age)
+                      ray_order, promote_waves, promote_age, cu_layout)
         o.results_mem = RT_MEM_DEVICE
         fa = FanArgs(fan)
         self.h = ctypes.c_void_p()

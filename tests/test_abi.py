@@ -149,22 +149,23 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
 def test_tune_cache_text_roundtrip(rt, tmp_path):
     """The autotuner's cache file format (host-only, no device)."""
     src = tmp_path / "tune.txt"
-    src.write_text("# comment\n256 181 181 226 0 0 1 17 16384 1 2 16 -1\n256 61 61 201 0 1 0 7 -1 2 1 0 0\n")
+    src.write_text("# comment\n256 181 181 226 0 0 1 17 16384 1 2 16 -1 2\n256 61 61 201 0 1 0 7 -1 2 1 0 0 0\n")
     rt.tune_cache_clear()
     rt.tune_cache_load(str(src))
     dst = tmp_path / "out.txt"
     rt.tune_cache_save(str(dst))
     lines = [l for l in dst.read_text().splitlines() if not l.startswith("#")]
-    assert sorted(lines) == sorted(["256 181 181 226 0 0 1 17 16384 1 2 16 -1",
-                                    "256 61 61 201 0 1 0 7 -1 2 1 0 0"])
+    assert sorted(lines) == sorted(["256 181 181 226 0 0 1 17 16384 1 2 16 -1 2",
+                                    "256 61 61 201 0 1 0 7 -1 2 1 0 0 0"])
     rt.tune_cache_clear()
     rt.tune_cache_save(str(dst))
     assert [l for l in dst.read_text().splitlines() if not l.startswith("#")] == []
 
 
-@pytest.mark.parametrize("bad", ["256 181 181\n", "1 2 3 4 5 6 7 8 9 1 3 0 0\n", "1 2 3 4 5 6 7 8 9 1 1\n",
-                                 "1 2 3 4 5 6 7 8 9 1 1 0 0 7\n", "a b c d e f g h i j k l m\n",
-                                 "1 2 3 4 5 6 7 8 9 1 1 65 0\n", "1 2 3 4 5 6 7 8 9 1 1 16 -2\n"])
+@pytest.mark.parametrize("bad", ["256 181 181\n", "1 2 3 4 5 6 7 8 9 1 3 0 0 0\n", "1 2 3 4 5 6 7 8 9 1 1\n",
+                                 "1 2 3 4 5 6 7 8 9 1 1 0 0 0 7\n", "a b c d e f g h i j k l m n\n",
+                                 "1 2 3 4 5 6 7 8 9 1 1 65 0 0\n", "1 2 3 4 5 6 7 8 9 1 1 16 -2 0\n",
+                                 "1 2 3 4 5 6 7 8 9 1 1 16 0 3\n", "1 2 3 4 5 6 7 8 9 1 1 16 0\n"])
 def test_tune_cache_rejects_malformed_lines(rt, tmp_path, bad):
     p = tmp_path / "bad.txt"
     p.write_text(bad)

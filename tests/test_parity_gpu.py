@@ -321,7 +321,8 @@ def test_invalid_arguments(rt, ctx, iso_wl, iso_grid, aniso_wl, aniso_grid):
         gpu_trace(rt, ctx, iso_grid, iso_wl, high_tx)
     assert e.value.code == rt.RT_E_UNSUPPORTED
     for kw in (dict(promote_waves=65), dict(promote_waves=-2), dict(promote_age=-2),
-               dict(ray_order=3), dict(waves_per_simd=3), dict(tail_threshold=-3)):
+               dict(ray_order=3), dict(waves_per_simd=3), dict(tail_threshold=-3),
+               dict(cu_layout=3), dict(cu_layout=-1)):
         with pytest.raises(rt.RTError) as e:
             gpu_trace(rt, ctx, iso_grid, iso_wl, **kw)
         assert e.value.code == rt.RT_E_INVALID, kw
@@ -384,15 +385,16 @@ def test_tail_kernel_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
 def test_promotion_is_bit_identical(rt, ctx, precision):
     """Promotion waves take trapped, grazing and old rays over while the
     one-lane waves run; outputs are identical with promotion off, at the
-    default (16 waves for this fan, trapped and grazing rays), with the most
-    waves, with a small age (many rays promoted, the queue kept full), and
-    with the tail kernel off (promoted rays run to the end)."""
+    default (16 waves for this fan, trapped and grazing rays, one four-wave
+    work-group per CU), with one-wave work-groups, with the most waves, with
+    a small age (many rays promoted, the queue kept full), and with the tail
+    kernel off (promoted rays run to the end)."""
     wl = synth.ionogram_workload(0)
     grid = rt.Grid(ctx, wl.grid)
     try:
         runs = [host(gpu_trace(rt, ctx, grid, wl, precision=precision, device_results=True,
                                **kw))
-                for kw in (dict(promote_waves=-1), dict(), dict(promote_waves=64),
+                for kw in (dict(promote_waves=-1), dict(), dict(cu_layout=1), dict(promote_waves=64),
                            dict(promote_waves=8, promote_age=200),
                            dict(promote_waves=4, promote_age=-1, tail_threshold=-1))]
     finally:
