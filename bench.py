@@ -145,6 +145,59 @@ def roofline(res, modes, run, wl, precision):
             "per_kernel": per_kernel}
 
 
+def gd_vs_cr(rtgd, ctx, a, wl):
+    """The paper's comparison of its GD interpolant with Catmull-Rom (Sec.
+    IV-B eq. rmse_metrics; Table II) on media with an exact reference: a
+    Chapman layer (foF2 8 MHz, 300 km, H 50 km) gridded at the isotropic
+    workload's spacing (0.5 deg, 2.2 km) and at 10 km, traced on the GPU with
+    both interpolants, against the oracle's analytic Chapman layer; without
+    the field, and with the dipole in the O and X modes (azimuth 45 deg, so
+    that the azimuth deviation is not zero by symmetry).  RMS errors over rays
+    with the same status in both.  Cost: the GPU time of the ionogram sweep
+    and of the 24,576-ray fan with CR over GD (same settings)."""
+    from oracle import oracle as O
+    from paper_2506_18579_amd import synth
+    elev = np.arange(1.0, 90.0, 1.0)
+    ana = O.OracleMedium.chapman(8.0, 300.0, 50.0, floor_km=60.0)
+    acc = {}
+    for dh in (2.2, 10.0):
+        geom = synth.GridGeom(61, 61, int(round(440.0 / dh)) + 1, 15.0, 0.5, 95.0, 0.5, 60.0, dh)
+        for label, B0, mode, az in (("iso", 0.0, 1, 0.0), ("O", synth.B0_DIPOLE_T, 1, 45.0),
+                                    ("X", synth.B0_DIPOLE_T, -1, 45.0)):
+            gr = synth.chapman_grid(geom, 8.0, 300.0, 50.0)
+            gr.B0_T = B0
+            fan = synth.Fan(30.0, 110.0, 0.0, elev, np.array([az]), np.array([10.0]), (mode,))
+            ref = O.trace(ana, elev, az, 10.0, np.full(elev.size, mode, np.int32), B0=B0,
+                          tx=(30.0, 110.0, 0.0), step=1.0, max_group=4000.0, exit_h=500.0)
+            row = {}
+            for interp in ("gd", "cr"):
+                g = rtgd.Grid(ctx, gr, interp=interp)
+                r = rtgd.trace(ctx, g, fan, step_km=1.0, max_group_km=4000.0, exit_h_km=500.0)
+                g.close()
+                same = (r["status"] == ref["status"]) & (ref["status"] != 3)
+                row[interp] = {k: float(np.sqrt(np.mean((r[k][same] - ref[k][same]) ** 2)))
+                               for k in ("group_km", "range_km", "az_dev_deg")}
+                row[interp]["rays"] = int(same.sum())
+            acc[f"dh{dh:g}km_{label}"] = row
+    cost = {}
+    for name, w in (("ionogram_112400", wl), ("aniso_fan_24576", synth.aniso_fan_workload(0))):
+        ms = {}
+        for interp in ("gd", "cr"):
+            g = rtgd.Grid(ctx, w.grid, interp=interp)
+            t = []
+            for rep in range(4):
+                r = rtgd.trace(ctx, g, w.fan, step_km=w.step_km, max_group_km=w.max_group_km,
+                               exit_h_km=w.exit_km, device_results=True)
+                if rep:
+                    t.append(r["kernel_ms"])
+            g.close()
+            ms[interp] = float(np.median(t))
+        cost[name] = {"gd_ms": ms["gd"], "cr_ms": ms["cr"], "cr_over_gd": ms["cr"] / ms["gd"]}
+    return {"rmse_vs_analytic_chapman": acc, "gpu_time": cost,
+            "note": "RMS of GPU results against the oracle's analytic layer, per interpolant; "
+                    "89 rays at 1-89 deg, 10 MHz; device time, median of 3 (FP64)"}
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -286,6 +339,8 @@ def main():
         accuracy["fp64_failures_first"] = r64["failures"][:3]
         accuracy["mixed_failures_first"] = r32["failures"][:3]
 
+    gdcr = None if a.no_cpu else gd_vs_cr(rtgd, ctx, a, wl)
+
     lat = np.array(fan64["walls"]) * 1e3
     lat32 = np.array(fan32["walls"]) * 1e3
     latt = np.array(fan64t["walls"]) * 1e3
@@ -316,6 +371,7 @@ def main():
                                     "note": "fan upload, the four kernels and the 8 MB result copy "
                                             "to pageable host memory"},
         "accuracy": accuracy,
+        "gd_vs_cr": gdcr,
         "mixed": {"value": mixed["ray_steps"] / mixed["elapsed"],
                   "kernel_ms_avg": float(np.mean(mixed["kernel_ms"])),
                   "speedup_vs_fp64": (mixed["ray_steps"] / mixed["elapsed"]) / value,

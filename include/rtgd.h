@@ -132,7 +132,10 @@ typedef struct {
                                2 = strided: q -> q * s mod n_rays with s
                                coprime to n_rays near 0.618 n_rays, which
                                spreads neighbouring (similar) rays over
-                               many waves                                  */
+                               many waves; 3 = sorted by wave mode (a
+                               counting sort, stable in ray index: O and
+                               isotropic rays, then X rays), so that a wave
+                               holds rays of one mode                     */
     int32_t promote_waves;  /* scheduling knob, results unchanged: this many
                                waves run rays 16 lanes each beside the
                                one-lane waves, taking over rays trapped in a
@@ -375,7 +378,8 @@ void rt_plan_destroy(rt_plan *plan);
  * tail_threshold, waves_per_simd, ray_order, promote_waves, promote_age and
  * cu_layout (see rt_trace_opts).  rt_autotune traces the given fan for every
  * candidate setting (tail_threshold in {-2, -1, 8 and 16 rays per CU} x
- * waves_per_simd in {1, 2} x ray_order in {index, strided}; then, on top of
+ * waves_per_simd in {1, 2} x ray_order in {index, strided, mode-sorted};
+ * then, on top of
  * the fastest of those unless it is the in-wave switch, promote_waves in
  * {16, 32, 64} with promote_age -1, each with cu_layout 2 and 1; the first
  * stage runs without promotion; one untimed run, then the median device

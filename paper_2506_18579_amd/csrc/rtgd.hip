@@ -388,6 +388,7 @@ struct TraceJob {
     int tail = 0;              // launch-wide hand-off threshold actually used (0: none)
     int inwave = 0;            // in-wave switch to 16 lanes per ray
     int64_t perm = 1;          // visiting stride
+    bool binned = false;       // queue sorted by wave mode
     int occ = 1;               // register budget variant
     int promote = 0;           // promotion waves (0: none)
     int promote_age = 0;       // promote rays of at least this many steps too (0: trapped and grazing rays only)
@@ -428,7 +429,7 @@ static_assert(sizeof(Counters) % 64 == 0, "counters fill whole cache lines");
 // (the hand-off buffer is device only): fan axes | segments | parameter
 // block | counters + per-segment steps | hand-off buffer.
 struct Layout {
-    size_t seg, par, cnt, steps, hand, rec, ids, host_bytes, dev_bytes;
+    size_t seg, par, cnt, steps, hand, rec, ids, order, host_bytes, dev_bytes;
 };
 
 size_t fan_values(const rt_fan &f) { return size_t(f.n_elev) + f.n_az + f.n_freq; }
@@ -446,7 +447,8 @@ Layout job_layout(const TraceJob &j)
     L.host_bytes = L.hand;
     L.rec = L.hand + align_up(size_t(j.tail) * sizeof(Handoff), 256);
     L.ids = L.rec + align_up(size_t(j.n_rays) * sizeof(RayRec), 256);
-    L.dev_bytes = L.ids + size_t(j.n_rays) * sizeof(int32_t) + 256;
+    L.order = L.ids + align_up(size_t(j.n_rays) * sizeof(int32_t), 256);
+    L.dev_bytes = L.order + (j.binned ? size_t(j.n_rays) * sizeof(int32_t) : 0) + 256;
     return L;
 }
 
@@ -473,8 +475,8 @@ rt_status validate_request(rt_ctx *ctx, const rt_grid *grid, const rt_fan *fan,
         return fail(ctx, RT_E_INVALID, "tail_threshold must be in [-2, 2^24]");
     if (opts->waves_per_simd < 0 || opts->waves_per_simd > 2)
         return fail(ctx, RT_E_INVALID, "waves_per_simd must be 0, 1 or 2");
-    if (opts->ray_order < 0 || opts->ray_order > 2)
-        return fail(ctx, RT_E_INVALID, "ray_order must be 0, 1 or 2");
+    if (opts->ray_order < 0 || opts->ray_order > 3)
+        return fail(ctx, RT_E_INVALID, "ray_order must be 0, 1, 2 or 3");
     if (opts->promote_waves < -1 || opts->promote_waves > kMaxPromoteWaves)
         return fail(ctx, RT_E_INVALID, "promote_waves must be in [-1, 64]");
     if (opts->promote_age < -1)
@@ -531,6 +533,7 @@ void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
     job.inwave = tail == -2 ? 1 : 0;
     job.tail = tail > 0 ? int(std::min<int64_t>(tail, n64)) : 0;
     job.perm = opts.ray_order == 2 ? visit_stride(n64) : 1;
+    job.binned = opts.ray_order == 3;
     // promotion runs beside the one-lane waves; not with the in-wave switch
     const int pw = opts.promote_waves != 0 ? opts.promote_waves
                  : (n64 >= kDefaultPromoteMinRays ? kDefaultPromoteWaves : 0);
@@ -618,6 +621,7 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.handoff_threshold = job.tail;
     P.inwave = job.inwave;
     P.perm_stride = job.perm;
+    P.order = job.binned ? reinterpret_cast<int32_t *>(dev + lay.order) : nullptr;
 }
 
 // Enqueue one launch on `stream`: stage fan axes, segment table, parameter
@@ -637,6 +641,17 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
     Segment *h_seg = reinterpret_cast<Segment *>(host + lay.seg);
     size_t off = 0;
     int start = 0;
+    // mode-sorted queue: rays of the first group (O or isotropic) of all
+    // segments, then the X rays; each segment's share of a group is its rays
+    // of that mode
+    auto x_rays = [](const JobSeg &js) -> int {
+        if (js.grid->B0 == 0.0) return 0;
+        const int nm = popcount_modes(js.fan.modes);
+        return nm == 2 ? js.n_rays / 2 : ((js.fan.modes & RT_MODE_O) ? 0 : js.n_rays);
+    };
+    int n_first = 0;
+    for (size_t k = 0; k < job.n_segs(); ++k) n_first += job.seg(k).n_rays - x_rays(job.seg(k));
+    int first_at = 0, x_at = n_first;
     const bool mixed = job.opts.precision == RT_MIXED;
     for (size_t k = 0; k < job.n_segs(); ++k) {
         const JobSeg &js = job.seg(k);
@@ -662,6 +677,10 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         S.mode_first = (f.modes & RT_MODE_O) ? 1 : -1;
         S.start = start;
         S.n = js.n_rays;
+        S.bin_pos[0] = first_at;
+        S.bin_pos[1] = x_at;
+        first_at += js.n_rays - x_rays(js);
+        x_at += x_rays(js);
         start += js.n_rays;
         off += fan_values(f);
     }
@@ -1576,7 +1595,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     r.n_steps = r.status + N;
     const int tails[4] = {-2, -1, ctx->n_cu * 8, ctx->n_cu * 16};
     const int occs[2] = {1, 2};
-    const int orders[2] = {1, 2};
+    const int orders[3] = {1, 2, 3};
     // one untimed run, then the median of three
     auto time_opts = [&](rt_trace_opts o, double &ms) -> rt_status {
         o.results_mem = RT_MEM_DEVICE;
@@ -1700,7 +1719,7 @@ extern "C" rt_status rt_tune_cache_load(const char *path)
         std::string rest;
         if (ss >> rest) return RT_E_INVALID;
         if (v.waves_per_simd < 0 || v.waves_per_simd > 2 || v.tail_threshold > (1 << 24) ||
-            v.tail_threshold < -2 || v.ray_order < 0 || v.ray_order > 2 || v.promote_waves < -1 ||
+            v.tail_threshold < -2 || v.ray_order < 0 || v.ray_order > 3 || v.promote_waves < -1 ||
             v.promote_waves > kMaxPromoteWaves || v.promote_age < -1 || v.cu_layout < 0 || v.cu_layout > 2)
             return RT_E_INVALID;
         loaded[k] = v;

@@ -44,6 +44,8 @@ struct Segment {
     int32_t n_elev, n_az, n_mode;
     int32_t mode_first;              // +1 if the first mode is O, -1 if X
     int32_t start, n;
+    int32_t bin_pos[2];              // mode-sorted queue: where this segment's O (or isotropic)
+                                     // rays and its X rays begin
 };
 
 template <typename T>
@@ -74,6 +76,7 @@ struct TraceParams {
                                // also the hand-off buffer capacity
     int32_t inwave;            // a drained wave with <= 4 live rays finishes them 16 lanes each
     int64_t perm_stride;       // launch ray q is visited as (q * perm_stride) mod n_rays
+    int32_t *order;            // if set: queue entry q holds launch ray order[q] (mode-sorted)
     // promotion: waves with block index >= n_producers run promoted rays
     // sixteen lanes each while the other waves still run one lane per ray
     int32_t n_producers;       // one-lane waves (all waves when promotion is off)
@@ -581,9 +584,10 @@ __device__ __forceinline__ int claim_promoted(const TraceParams<T> &P)
 
 // Persistent one-lane-per-ray kernel.  Each 64-lane wave loops { refill
 // idle lanes from the queue; one RK4 step on every live lane } until the
-// queue is drained and every lane is idle.  Rays are visited in the order
-// (q * perm_stride) mod n_rays, which spreads runs of neighbouring (and
-// similarly long) rays over many waves.  Once the queue is drained, either
+// queue is drained and every lane is idle.  Rays are visited in index order,
+// in the order (q * perm_stride) mod n_rays, which spreads runs of
+// neighbouring (and similarly long) rays over many waves, or sorted by wave
+// mode (order, written by k_start).  Once the queue is drained, either
 //   * (inwave) a wave left with at most four live rays moves them onto its
 //     four 16-lane rows and finishes them there, or
 //   * (handoff_threshold > 0) once at most handoff_threshold rays are live
@@ -609,8 +613,9 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
             int q = wave_append(P.queue_head, need, lane);
             if (need) {
                 if (q < P.n_rays) {
-                    ray = int((unsigned long long)q * (unsigned long long)P.perm_stride %
-                              (unsigned long long)P.n_rays);
+                    ray = P.order ? P.order[q]
+                                  : int((unsigned long long)q * (unsigned long long)P.perm_stride %
+                                        (unsigned long long)P.n_rays);
                     L = P.rec[ray].L;
                 } else {
                     ray = -2;
@@ -851,6 +856,20 @@ __device__ __forceinline__ void start_body(const TraceParams<T> &P)
     rec.L = L;
     rec.status = -1;
     if (P.promo_ids) P.promo_ids[ray] = -1;
+    if (P.order) {
+        // Counting sort of the queue by wave mode, stable in ray index: O and
+        // isotropic rays first, then X rays.  The counts follow from the fans'
+        // shapes, so each ray's place is computed, not counted: within a
+        // segment with both modes, mode m of frequency i_f holds rays
+        // i_f * n_elev * n_az + j of its group; otherwise the segment's rays
+        // keep their order.
+        const Segment &S = P.seg[L.seg];
+        const int ea = S.n_elev * S.n_az;
+        const int i = L.local;
+        const int grp = L.rc.sigma < 0 ? 1 : 0;
+        const int pos = (S.n_mode == 2 && L.rc.sigma != 0) ? (i / (2 * ea)) * ea + i % ea : i;
+        P.order[S.bin_pos[grp] + pos] = ray;
+    }
 }
 
 // Outputs of every launch ray (one thread per ray), after the trace kernels,

@@ -162,7 +162,7 @@ def test_tune_cache_text_roundtrip(rt, tmp_path):
     assert [l for l in dst.read_text().splitlines() if not l.startswith("#")] == []
 
 
-@pytest.mark.parametrize("bad", ["256 181 181\n", "1 2 3 4 5 6 7 8 9 1 3 0 0 0\n", "1 2 3 4 5 6 7 8 9 1 1\n",
+@pytest.mark.parametrize("bad", ["256 181 181\n", "1 2 3 4 5 6 7 8 9 1 4 0 0 0\n", "1 2 3 4 5 6 7 8 9 1 1\n",
                                  "1 2 3 4 5 6 7 8 9 1 1 0 0 0 7\n", "a b c d e f g h i j k l m n\n",
                                  "1 2 3 4 5 6 7 8 9 1 1 65 0 0\n", "1 2 3 4 5 6 7 8 9 1 1 16 -2 0\n",
                                  "1 2 3 4 5 6 7 8 9 1 1 16 0 3\n", "1 2 3 4 5 6 7 8 9 1 1 16 0\n"])

@@ -321,7 +321,7 @@ def test_invalid_arguments(rt, ctx, iso_wl, iso_grid, aniso_wl, aniso_grid):
         gpu_trace(rt, ctx, iso_grid, iso_wl, high_tx)
     assert e.value.code == rt.RT_E_UNSUPPORTED
     for kw in (dict(promote_waves=65), dict(promote_waves=-2), dict(promote_age=-2),
-               dict(ray_order=3), dict(waves_per_simd=3), dict(tail_threshold=-3),
+               dict(ray_order=4), dict(waves_per_simd=3), dict(tail_threshold=-3),
                dict(cu_layout=3), dict(cu_layout=-1)):
         with pytest.raises(rt.RTError) as e:
             gpu_trace(rt, ctx, iso_grid, iso_wl, **kw)
@@ -394,7 +394,8 @@ def test_promotion_is_bit_identical(rt, ctx, precision):
     try:
         runs = [host(gpu_trace(rt, ctx, grid, wl, precision=precision, device_results=True,
                                **kw))
-                for kw in (dict(promote_waves=-1), dict(), dict(cu_layout=1), dict(promote_waves=64),
+                for kw in (dict(promote_waves=-1), dict(), dict(cu_layout=1), dict(ray_order=3),
+                           dict(promote_waves=64),
                            dict(promote_waves=8, promote_age=200),
                            dict(promote_waves=4, promote_age=-1, tail_threshold=-1))]
     finally:
@@ -414,3 +415,39 @@ def test_single_ray_is_handed_off(rt, ctx, aniso_wl, aniso_grid):
     b = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan, tail_threshold=1)
     for k in ("group_km", "range_km", "az_dev_deg", "status", "n_steps"):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_mode_sorted_queue_is_result_neutral(rt, ctx, iso_wl, iso_grid, aniso_wl, aniso_grid):
+    """The queue sorted by wave mode (ray_order 3: a counting sort, O and
+    isotropic rays first, then X) gives the same outputs as index order for
+    fans with both modes, one mode, and no field; and in a server launch that
+    batches requests of different mode sets, each result equals its fan
+    traced alone."""
+    base = aniso_wl.fan
+    fans = [(aniso_grid, aniso_wl, synth.sub_fan(base, elev_idx=list(range(0, 64, 5)),
+                                                 az_idx=[3, 40], freq_idx=[0, 1])),
+            (aniso_grid, aniso_wl, synth.sub_fan(base, elev_idx=list(range(0, 64, 7)), az_idx=[9],
+                                                 modes=(-1,))),
+            (aniso_grid, aniso_wl, synth.sub_fan(base, elev_idx=list(range(2, 64, 7)), az_idx=[20],
+                                                 modes=(1,))),
+            (iso_grid, iso_wl, iso_wl.fan)]
+    for grid, wl, fan in fans:
+        a = gpu_trace(rt, ctx, grid, wl, fan, ray_order=1)
+        b = gpu_trace(rt, ctx, grid, wl, fan, ray_order=3)
+        for k in ("group_km", "phase_km", "range_km", "az_dev_deg", "status", "n_steps"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
+    srv = rt.Server(ctx, n_slots=1, mem_budget_bytes=64 << 20)
+    try:
+        kw = dict(step_km=1.0, max_group_km=4000.0, exit_h_km=600.0, ray_order=3)
+        ids = {srv.submit(aniso_grid, f, **kw): f for _, _, f in fans[:3]}
+        done = {}
+        while len(done) < len(ids):
+            for d in srv.poll():
+                done[d["id"]] = d
+        for rid, f in ids.items():
+            got = srv.fetch(rid, done[rid]["n_rays"])
+            alone = rt.trace(ctx, aniso_grid, f, **kw)
+            for k in ("group_km", "range_km", "status", "n_steps"):
+                assert np.array_equal(got[k], alone[k], equal_nan=True), k
+    finally:
+        srv.close()
