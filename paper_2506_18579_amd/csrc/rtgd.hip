@@ -147,6 +147,30 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+// The trace kernels of one precision and variant (bit 0: Catmull-Rom
+// interpolation, bit 1: every ray anisotropic).
+struct KernelSet {
+    const void *trace, *trace_w2, *trace_g, *tail, *tail_w2;
+};
+
+template <typename T, int V>
+KernelSet kernel_set_of()
+{
+    return {(const void *)k_trace<T, V>, (const void *)k_trace_w2<T, V>, (const void *)k_trace_g<T, V>,
+            (const void *)k_tail<T, V>, (const void *)k_tail_w2<T, V>};
+}
+
+template <typename T>
+KernelSet kernel_set(int variant)
+{
+    switch (variant & 3) {
+    case 0: return kernel_set_of<T, 0>();
+    case 1: return kernel_set_of<T, 1>();
+    case 2: return kernel_set_of<T, 2>();
+    default: return kernel_set_of<T, 3>();
+    }
+}
+
 extern "C" {
 
 void rt_default_opts(rt_trace_opts *o)
@@ -227,15 +251,13 @@ rt_status rt_ctx_create(int32_t device, void *stream, rt_ctx **out)
     {
         const size_t per_cu = prop.maxSharedMemoryPerMultiProcessor;
         const size_t lock = per_cu / 2 + 4096;
-        if (per_cu > 0 && lock <= prop.sharedMemPerBlock &&
-            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<double, 0>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess &&
-            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<double, 1>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess &&
-            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<float, 0>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess &&
-            hipFuncSetAttribute(reinterpret_cast<const void *>(k_trace_g<float, 1>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lock)) == hipSuccess)
+        bool ok = per_cu > 0 && lock <= prop.sharedMemPerBlock;
+        for (int v = 0; ok && v < 4; ++v)
+            ok = hipFuncSetAttribute(kernel_set<double>(v).trace_g, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     int(lock)) == hipSuccess &&
+                 hipFuncSetAttribute(kernel_set<float>(v).trace_g, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     int(lock)) == hipSuccess;
+        if (ok)
             c->lds_lock = int(lock);
     }
     int wall = 0;
@@ -580,6 +602,7 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.r0 = gq.earth_radius_km + fan->tx_h_km;
     P.step = opts->step_km;
     P.step6 = opts->step_km / 6.0;
+    P.short_step = series_covers_step(opts->step_km, gq.earth_radius_km) ? 1 : 0;
     P.max_group = opts->max_group_km;
     P.exit_h = opts->exit_h_km > 0 ? opts->exit_h_km : gq.h0_km + (gq.n_h - 1) * gq.dh_km;
     P.floor_h = gq.h0_km;
@@ -684,30 +707,17 @@ rt_status enqueue_job(rt_ctx *ctx, hipStream_t stream, const TraceJob &job, char
         start += js.n_rays;
         off += fan_values(f);
     }
-    const bool cr = job.seg(0).grid->geom.interp == RT_INTERP_CR;
-    const int occ = job.occ;
-    const void *kt;
-    const void *ktg;  // the one-lane kernel grouped four waves per work-group
-    const void *kl;
-    const void *ks;   // starting states
-    const void *kf;   // outputs
-    if (mixed) {
-        ks = (const void *)k_start<float>;
-        kf = (const void *)k_finish<float>;
-        kt = occ == 2 ? (cr ? (const void *)k_trace_w2<float, 1> : (const void *)k_trace_w2<float, 0>)
-                      : (cr ? (const void *)k_trace<float, 1> : (const void *)k_trace<float, 0>);
-        ktg = cr ? (const void *)k_trace_g<float, 1> : (const void *)k_trace_g<float, 0>;
-        kl = occ == 2 ? (cr ? (const void *)k_tail_w2<float, 1> : (const void *)k_tail_w2<float, 0>)
-                      : (cr ? (const void *)k_tail<float, 1> : (const void *)k_tail<float, 0>);
-    } else {
-        ks = (const void *)k_start<double>;
-        kf = (const void *)k_finish<double>;
-        kt = occ == 2 ? (cr ? (const void *)k_trace_w2<double, 1> : (const void *)k_trace_w2<double, 0>)
-                      : (cr ? (const void *)k_trace<double, 1> : (const void *)k_trace<double, 0>);
-        ktg = cr ? (const void *)k_trace_g<double, 1> : (const void *)k_trace_g<double, 0>;
-        kl = occ == 2 ? (cr ? (const void *)k_tail_w2<double, 1> : (const void *)k_tail_w2<double, 0>)
-                      : (cr ? (const void *)k_tail<double, 1> : (const void *)k_tail<double, 0>);
-    }
+    // kernel variant: interpolation, and whether every ray is anisotropic
+    bool aniso = true;
+    for (size_t k = 0; k < job.n_segs(); ++k) aniso = aniso && job.seg(k).grid->B0 != 0.0;
+    const int variant = (job.seg(0).grid->geom.interp == RT_INTERP_CR ? 1 : 0) | (aniso ? 2 : 0);
+    const KernelSet ksel = mixed ? kernel_set<float>(variant) : kernel_set<double>(variant);
+    const bool occ2 = job.occ == 2;
+    const void *kt = occ2 ? ksel.trace_w2 : ksel.trace;
+    const void *ktg = ksel.trace_g;  // the one-lane kernel grouped four waves per work-group
+    const void *kl = occ2 ? ksel.tail_w2 : ksel.tail;
+    const void *ks = mixed ? (const void *)k_start<float> : (const void *)k_start<double>;  // starting states
+    const void *kf = mixed ? (const void *)k_finish<float> : (const void *)k_finish<double>;  // outputs
     // One-lane waves first, promotion waves after them: blocks are
     // dispatched in index order, so a promotion wave runs only once every
     // one-lane wave is resident.  All of them fit at once on an idle GPU.

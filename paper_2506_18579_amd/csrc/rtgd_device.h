@@ -93,20 +93,25 @@ struct Piece {
     T d[5];   // w' = sum d[k] s^k, d[k] = (k + 1) c[k + 1]
 };
 
+// Kernel variant: bit 0 is the interpolation (0 GD, 1 Catmull-Rom), bit 1
+// says that every ray of the launch is anisotropic (a field is set), so the
+// isotropic branch of the right-hand side is compiled out.
+constexpr int interp_of(int V) { return V & 1; }
+constexpr bool aniso_only(int V) { return (V & 2) != 0; }
+
 template <typename T, int IP>
 __device__ __forceinline__ Piece<T> piece(int a)
 {
+    using B = Basis<interp_of(IP)>;
     Piece<T> p;
 #pragma unroll
-    for (int k = 0; k <= Basis<IP>::DEG; ++k) {
-        double v = a == 0 ? Basis<IP>::c[0][k] : a == 1 ? Basis<IP>::c[1][k]
-                 : a == 2 ? Basis<IP>::c[2][k] : Basis<IP>::c[3][k];
+    for (int k = 0; k <= B::DEG; ++k) {
+        double v = a == 0 ? B::c[0][k] : a == 1 ? B::c[1][k] : a == 2 ? B::c[2][k] : B::c[3][k];
         p.c[k] = T(v);
     }
 #pragma unroll
-    for (int k = 0; k < Basis<IP>::DEG; ++k) {
-        double v = a == 0 ? Basis<IP>::c[0][k + 1] : a == 1 ? Basis<IP>::c[1][k + 1]
-                 : a == 2 ? Basis<IP>::c[2][k + 1] : Basis<IP>::c[3][k + 1];
+    for (int k = 0; k < B::DEG; ++k) {
+        double v = a == 0 ? B::c[0][k + 1] : a == 1 ? B::c[1][k + 1] : a == 2 ? B::c[2][k + 1] : B::c[3][k + 1];
         p.d[k] = T(v * double(k + 1));
     }
     return p;
@@ -115,7 +120,7 @@ __device__ __forceinline__ Piece<T> piece(int a)
 template <typename T, int IP>
 __device__ __forceinline__ void eval_piece(const Piece<T> &p, T s, T &w, T &dw)
 {
-    constexpr int D = Basis<IP>::DEG;
+    constexpr int D = Basis<interp_of(IP)>::DEG;
     T x = p.c[D];
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) x = fm(x, s, p.c[k]);
@@ -481,7 +486,7 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
     const T n2 = fm(nr, nr, fm(nt, nt, np * np));
 
     T G, Hn0, Hn1, Hn2, Hr, Hth, Hph;
-    if (rc.sigma == 0) {
+    if (!aniso_only(IP) && rc.sigma == 0) {
         // mu^2 = 1 - X: dH/dn = n, G = -n.n - X, dH/dq = X_q / 2
         G = -n2 - X;
         Hn0 = nr; Hn1 = nt; Hn2 = np;
@@ -554,6 +559,12 @@ __device__ __forceinline__ Anchor make_anchor(double th)
     return Anchor{th, q.s, q.c};
 }
 
+// Steps for which every RK4 stage stays within kSeriesMax of the anchor: the
+// step starts within kAnchorMove of it, and a stage lies at most h |dth/dP'|
+// further, with |dth/dP'| <= |dx/dP'| / r <= 1 / R (the group speed is at
+// most c) -- h <= R / 60 leaves a margin of 50 % on that slope.
+__host__ __device__ inline bool series_covers_step(double h_km, double R_km) { return h_km <= R_km / 60.0; }
+
 // One fixed RK4 step of size h (always FP64 state and combination); h6 is
 // h / 6, rounded once by the caller.  UNROLL = false: the four stages share
 // one copy of the right-hand side (a stage loop), which keeps register
@@ -566,7 +577,7 @@ __device__ __forceinline__ Anchor make_anchor(double th)
 // stage beyond that uses the library.
 template <typename T, int IP, int LANES, bool UNROLL = false>
 __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc, double y[7], double h,
-                                         double h6, Anchor &an, StencilCache<T, LANES> &sc)
+                                         double h6, bool short_step, Anchor &an, StencilCache<T, LANES> &sc)
 {
     double k[7], acc[7], t[7];
     bool ok = true;
@@ -576,7 +587,9 @@ __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc
     auto stage_body = [&](int stage) {
         const double d = t[1] - an.th;
         double st, ct;
-        if (fabs(d) <= kSeriesMax) {
+        // short_step (uniform over the launch): every stage is within
+        // kSeriesMax of the anchor, so no lane needs the library
+        if (short_step || fabs(d) <= kSeriesMax) {
             sincos_add(an.s, an.c, d, st, ct);
         } else {
             const SinCos q = sincos_ref(t[1]);

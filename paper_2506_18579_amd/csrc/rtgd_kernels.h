@@ -58,6 +58,7 @@ struct TraceParams {
     double up[3], north[3], east[3];   // transmitter frame (Cartesian)
     double r0;                 // R + tx height
     double step, step6;        // step and step / 6 (km)
+    int32_t short_step;        // every RK4 stage within the anchor series (series_covers_step)
     double max_group, exit_h, floor_h;
     int32_t max_steps;         // hard cap (never reached before max_group)
     int32_t traj_stride;
@@ -372,7 +373,7 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParam
                                        bool write, StencilCache<T, LANES> &sc)
 {
     const double nr0 = L.y[3];
-    bool ok = rk4_step<T, IP, LANES, UNROLL>(P.g, L.rc, L.y, P.step, P.step6, L.an, sc);
+    bool ok = rk4_step<T, IP, LANES, UNROLL>(P.g, L.rc, L.y, P.step, P.step6, P.short_step != 0, L.an, sc);
     L.gp += P.step;
     ++L.steps;
     const double h = L.y[0] - P.g.R;
