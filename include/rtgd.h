@@ -383,8 +383,10 @@ void rt_plan_destroy(rt_plan *plan);
  * the fastest of those unless it is the in-wave switch, promote_waves in
  * {16, 32, 64} with promote_age -1, each with cu_layout 2 and 1; the first
  * stage runs without promotion; one untimed run, then the median device
- * time of three), keeps the fastest if it beats the library defaults by at
- * least 2 % (else the defaults, all six fields 0) and writes base with
+ * time of three), times the fastest and the library defaults again, seven
+ * single launches each, interleaved, keeps the fastest if its median beats
+ * the defaults' by at least 2 % (else the defaults, all six fields 0;
+ * best_ms and default_ms are those medians) and writes base with
  * those six fields replaced to *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on
  * or off and the ray count rounded to a power of two; a cached key is

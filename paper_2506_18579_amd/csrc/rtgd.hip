@@ -1670,6 +1670,36 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
             }
         }
     }
+    // Confirmation: single launches vary by several per cent from run to run
+    // (the last rays' 16-lane steps set the launch time), so the winner and
+    // the defaults are timed again, interleaved, and the winner is kept only
+    // if its median is clearly below the defaults'.
+    if (st == RT_OK && !(bv.tail_threshold == 0 && bv.waves_per_simd == 0 && bv.ray_order == 0 &&
+                         bv.promote_waves == 0 && bv.promote_age == 0 && bv.cu_layout == 0)) {
+        rt_trace_opts ob = *base, od = *base;
+        ob.tail_threshold = bv.tail_threshold;
+        ob.waves_per_simd = bv.waves_per_simd;
+        ob.ray_order = bv.ray_order;
+        ob.promote_waves = bv.promote_waves;
+        ob.promote_age = bv.promote_age;
+        ob.cu_layout = bv.cu_layout;
+        od.tail_threshold = od.waves_per_simd = od.ray_order = 0;
+        od.promote_waves = od.promote_age = od.cu_layout = 0;
+        ob.results_mem = od.results_mem = RT_MEM_DEVICE;
+        double tb[7], td[7];
+        for (int rep = 0; rep < 7 && st == RT_OK; ++rep) {
+            st = rt_trace(ctx, grid, fan, &ob, &r);
+            tb[rep] = r.kernel_ms;
+            if (st == RT_OK) st = rt_trace(ctx, grid, fan, &od, &r);
+            td[rep] = r.kernel_ms;
+        }
+        if (st == RT_OK) {
+            std::sort(tb, tb + 7);
+            std::sort(td, td + 7);
+            best = tb[3];
+            inf.default_ms = td[3];
+        }
+    }
     (void)hipFree(buf);
     if (st != RT_OK) return st;
     // keep the library defaults unless a candidate is clearly faster

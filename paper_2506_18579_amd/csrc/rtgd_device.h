@@ -50,7 +50,7 @@ struct GridDev {
 struct RayConst {
     const void *v;   // grid values (T) of the ray's grid
     double inv_f2;   // 1 / f_MHz^2
-    double Y0;       // f_H at the equatorial surface / f (0: no field)
+    double YR3;      // (f_H at the equatorial surface / f) R^3, km^3 (0: no field)
     int32_t sigma;   // +1 O, -1 X, 0 isotropic
 };
 
@@ -448,15 +448,14 @@ __device__ __forceinline__ void appleton_partials(T X, T u, T a, T b, int sigma,
     const T iS = rsqrt(S2);
     const T S = S2 * iS;
     const T Tt = S + a;
-    const T iT = rcp(Tt);
-    const T iu = rcp(u);
-    const T k = o_mode ? T(2) * b * iT : T(-0.5) * Tt * (iu * iu);
+    const T x = rcp(o_mode ? Tt : u);     // O: 1/T, X: 1/u (the one each mode needs)
+    const T k = o_mode ? T(2) * b * x : T(-0.5) * Tt * (x * x);
     const T E = fm(k, u, T(1));
     const T iE = rcp(E);
     const T m = (o_mode ? -k : k) * iS;
     const T EX = a * m;
     const T Ea = u * m;
-    const T Eb = o_mode ? fm(T(-4) * bu * u * u * iS, iT * iT, T(2) * u * iT) : -(u * iS);
+    const T Eb = o_mode ? fm(T(-4) * bu * u * u * iS, x * x, T(2) * u * x) : -(u * iS);
     const T XiE2 = X * iE * iE;
     mX = fm(EX, XiE2, -iE);
     ma = Ea * XiE2;
@@ -481,7 +480,8 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
     const T Xr = Fr * inv_f2, Xth = Fth * inv_f2, Xph = Fph * inv_f2;
 
     const T rr = T(r);
-    const T ir = rcp(rr);
+    const T irs = rcp(rr * st);   // 1 / (r sin th)
+    const T ir = irs * st;
     const T nr = T(y[3]), nt = T(y[4]), np = T(y[5]);
     const T n2 = fm(nr, nr, fm(nt, nt, np * np));
 
@@ -494,8 +494,7 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
     } else {
         // axial dipole: Y_r = -2 Yc cos th, Y_th = -Yc sin th, Yc = Y0 (R/r)^3;
         // dY/dr = -3 Y / r (used below in closed form)
-        const T q = T(g.R) * ir;
-        const T Yc = T(rc.Y0) * (q * q * q);
+        const T Yc = T(rc.YR3) * (ir * ir * ir);
         const T Y0 = T(-2) * Yc * ct, Y1 = -Yc * st;
         const T Yt0 = T(2) * Yc * st, Yt1 = -Yc * ct;           // dY/dth
         const T Y2 = fm(Y0, Y0, Y1 * Y1);
@@ -528,7 +527,6 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
         Hph = T(-0.5) * (mX * Xph);
     }
     const T iG = rcp(G);
-    const T irs = ir * rcp(st);
     const T rdot = -Hn0 * iG;
     const T thdot = -Hn1 * iG * ir;
     const T phdot = -Hn2 * iG * irs;
@@ -587,14 +585,15 @@ __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc
     auto stage_body = [&](int stage) {
         const double d = t[1] - an.th;
         double st, ct;
+        sincos_add(an.s, an.c, d, st, ct);
         // short_step (uniform over the launch): every stage is within
         // kSeriesMax of the anchor, so no lane needs the library
-        if (short_step || fabs(d) <= kSeriesMax) {
-            sincos_add(an.s, an.c, d, st, ct);
-        } else {
-            const SinCos q = sincos_ref(t[1]);
-            st = q.s;
-            ct = q.c;
+        if (!short_step) {
+            if (!(fabs(d) <= kSeriesMax)) {
+                const SinCos q = sincos_ref(t[1]);
+                st = q.s;
+                ct = q.c;
+            }
         }
         ok &= ray_rhs<T, IP, LANES>(g, rc, t, T(st), T(ct), sc, k);
         // weights 1, 2, 2, 1 of the combination; next stage at y + c h k

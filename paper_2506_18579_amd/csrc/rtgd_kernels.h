@@ -221,7 +221,7 @@ __device__ __forceinline__ void ray_const(const TraceParams<T> &P, int ray, Lane
     int sigma = (im == 0) ? S.mode_first : -1;
     L.rc.v = S.v;
     L.rc.inv_f2 = 1.0 / (f * f);
-    L.rc.Y0 = kKB * S.B0 / (f * 1e6);
+    L.rc.YR3 = kKB * S.B0 / (f * 1e6) * (P.g.R * P.g.R * P.g.R);
     L.rc.sigma = (S.B0 == 0.0) ? 0 : sigma;
     L.az0 = S.az[ia];
 }
@@ -400,9 +400,11 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParam
         }
     }
     int status = -1;
-    bool finite = ok;
+    // y[i] * 0 is NaN exactly when y[i] is infinite or NaN, else +-0
+    double z = L.y[0] * 0.0;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) finite = finite && isfinite(L.y[i]);
+    for (int i = 1; i < 7; ++i) z = fm(L.y[i], 0.0, z);
+    const bool finite = ok && z == 0.0;
     if (!finite) {
         status = kNumeric;
     } else if (h < P.floor_h && L.y[3] < 0.0) {
@@ -502,7 +504,7 @@ __device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, L
     M.rc.v = reinterpret_cast<const void *>(
         __shfl((unsigned long long)reinterpret_cast<uintptr_t>(L.rc.v), s));
     M.rc.inv_f2 = __shfl(L.rc.inv_f2, s);
-    M.rc.Y0 = __shfl(L.rc.Y0, s);
+    M.rc.YR3 = __shfl(L.rc.YR3, s);
     M.rc.sigma = __shfl(L.rc.sigma, s);
     M.steps = __shfl(L.steps, s);
     M.ntraj = __shfl(L.ntraj, s);

@@ -27,6 +27,9 @@ def main():
     ap.add_argument("--promote-waves", type=int, default=0)
     ap.add_argument("--promote-age", type=int, default=0)
     ap.add_argument("--cu-layout", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner first and trace with the settings it picks "
+                         "(the knob options above are then ignored)")
     a = ap.parse_args()
     import torch
     from paper_2506_18579_amd import rtgd, synth
@@ -47,13 +50,17 @@ def main():
                            (int(md),))
     ctx = rtgd.Context(0)
     grid = rtgd.Grid(ctx, wl.grid)
+    wkw = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km)
+    knobs = dict(tail_threshold=a.tail, waves_per_simd=a.waves_per_simd, ray_order=a.ray_order,
+                 promote_waves=a.promote_waves, promote_age=a.promote_age, cu_layout=a.cu_layout)
+    if a.autotune:
+        tune = rtgd.autotune(ctx, grid, wl.fan, precision=a.precision, **wkw)
+        knobs = {k: tune[k] for k in knobs}
+        print(json.dumps({"autotuned": knobs}), flush=True)
     out = None
     for i in range(a.reps):
-        out = rtgd.trace(ctx, grid, wl.fan, step_km=wl.step_km, max_group_km=wl.max_group_km,
-                         exit_h_km=wl.exit_km, precision=a.precision, device_results=True, out=out,
-                         tail_threshold=a.tail, waves_per_simd=a.waves_per_simd, ray_order=a.ray_order,
-                         promote_waves=a.promote_waves, promote_age=a.promote_age,
-                         cu_layout=a.cu_layout)
+        out = rtgd.trace(ctx, grid, wl.fan, precision=a.precision, device_results=True, out=out,
+                         **wkw, **knobs)
         print(json.dumps({"rep": i, "workload": wl.name, "precision": a.precision,
                           "ray_steps": out["total_steps"], "kernel_ms": out["kernel_ms"],
                           "trace_ms": out["trace_ms"], "tail_ms": out["tail_ms"],
