@@ -156,11 +156,13 @@ __device__ __forceinline__ int locate(double t, double kmax, double &s, bool &cl
 
 // Reciprocal and reciprocal square root from the hardware estimates.  On
 // gfx950 v_rcp_f64 / v_rsq_f64 are good to about 24 bits (max relative error
-// 4.6e-8 / 5.2e-8 measured over 2^20 arguments), so one Newton step for the
-// reciprocal (x' = x + x (1 - a x), error ~ e^2 ~ 2e-15) and two for the
-// reciprocal square root (x' = x + x (1/2 - (a/2) x^2)) bring them to
-// FP64 working accuracy.  The FP32 estimates are within 1.5 ulp of FP32
-// (9.0e-8 / 9.3e-8) and are used as they are.
+// 4.6e-8 / 5.2e-8 measured over 2^20 arguments), so one Newton step each,
+// x' = x + x (1 - a x) for the reciprocal (relative error ~ e^2 ~ 2.1e-15)
+// and x' = x + x (1/2 - (a/2) x^2) for the reciprocal square root
+// (~ 1.5 e^2 ~ 4.1e-15), brings them to within a few times 1e-15, six
+// orders below the 1e-9 agreement asked of the FP64 path.  The FP32
+// estimates are within 1.5 ulp of FP32 (9.0e-8 / 9.3e-8) and are used as
+// they are.
 __device__ __forceinline__ double rcp(double a)
 {
     double x = __builtin_amdgcn_rcp(a);
@@ -171,10 +173,8 @@ __device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a);
 __device__ __forceinline__ double rsqrt(double a)
 {
     const double h = 0.5 * a;
-    double x = __builtin_amdgcn_rsq(a);
-    double e = fma(-h, x * x, 0.5);
-    x = fma(x, e, x);
-    e = fma(-h, x * x, 0.5);
+    const double x = __builtin_amdgcn_rsq(a);
+    const double e = fma(-h, x * x, 0.5);
     return fma(x, e, x);
 }
 __device__ __forceinline__ float rsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
@@ -443,22 +443,23 @@ template <typename T>
 __device__ __forceinline__ void appleton_partials(T X, T u, T a, T b, int sigma, T &mX, T &ma, T &mb)
 {
     const bool o_mode = sigma > 0;
-    const T bu = b * u;
-    const T S2 = fm(a, a, T(4) * bu * u);
+    const T w4 = T(4) * (b * u) * u;      // 4 b u^2
+    const T S2 = fm(a, a, w4);
     const T iS = rsqrt(S2);
     const T S = S2 * iS;
     const T Tt = S + a;
     const T x = rcp(o_mode ? Tt : u);     // O: 1/T, X: 1/u (the one each mode needs)
-    const T k = o_mode ? T(2) * b * x : T(-0.5) * Tt * (x * x);
+    const T xx = x * x;
+    const T k = o_mode ? T(2) * b * x : T(-0.5) * Tt * xx;
     const T E = fm(k, u, T(1));
     const T iE = rcp(E);
     const T m = (o_mode ? -k : k) * iS;
-    const T EX = a * m;
-    const T Ea = u * m;
-    const T Eb = o_mode ? fm(T(-4) * bu * u * u * iS, x * x, T(2) * u * x) : -(u * iS);
-    const T XiE2 = X * iE * iE;
-    mX = fm(EX, XiE2, -iE);
-    ma = Ea * XiE2;
+    const T ui = u * iS;
+    // O: 2u/T - 4 b u^3 / (S T^2) = 2 u x - 4 b u^2 (u / S) x^2
+    const T Eb = o_mode ? fm(-w4 * ui, xx, T(2) * u * x) : -ui;
+    const T XiE2 = (X * iE) * iE;
+    mX = fm(a * m, XiE2, -iE);
+    ma = (u * m) * XiE2;
     mb = Eb * XiE2;
 }
 
@@ -477,30 +478,36 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
     const double Xd = F * rc.inv_f2;
     const T X = T(Xd);
     const T u = T(1.0 - Xd);
-    const T Xr = Fr * inv_f2, Xth = Fth * inv_f2, Xph = Fph * inv_f2;
 
     const T rr = T(r);
-    const T irs = rcp(rr * st);   // 1 / (r sin th)
+    const T rst = rr * st;
+    const T irs = rcp(rst);       // 1 / (r sin th)
     const T ir = irs * st;
     const T nr = T(y[3]), nt = T(y[4]), np = T(y[5]);
     const T n2 = fm(nr, nr, fm(nt, nt, np * np));
 
+    // The medium enters dH/dq (q = r, th, ph) only as -1/2 mu^2_X dX/dq
+    // = sX F_q, with sX = -mu^2_X / (2 f^2).
     T G, Hn0, Hn1, Hn2, Hr, Hth, Hph;
     if (!aniso_only(IP) && rc.sigma == 0) {
         // mu^2 = 1 - X: dH/dn = n, G = -n.n - X, dH/dq = X_q / 2
         G = -n2 - X;
         Hn0 = nr; Hn1 = nt; Hn2 = np;
-        Hr = T(0.5) * Xr; Hth = T(0.5) * Xth; Hph = T(0.5) * Xph;
+        const T sX = T(0.5) * inv_f2;
+        Hr = sX * Fr; Hth = sX * Fth; Hph = sX * Fph;
     } else {
-        // axial dipole: Y_r = -2 Yc cos th, Y_th = -Yc sin th, Yc = Y0 (R/r)^3;
+        // axial dipole: Y_r = -2 Yc cos th, Y_th = -Yc sin th, Yc = Y0 (R/r)^3,
+        // so dY_th/dth = -Yc cos th = Y_r / 2 and dY_r/dth = -2 Y_th;
         // dY/dr = -3 Y / r (used below in closed form)
         const T Yc = T(rc.YR3) * (ir * ir * ir);
-        const T Y0 = T(-2) * Yc * ct, Y1 = -Yc * st;
-        const T Yt0 = T(2) * Yc * st, Yt1 = -Yc * ct;           // dY/dth
+        const T Y1 = -(Yc * st);
+        const T Yt1 = -(Yc * ct);    // dY_th/dth
+        const T Y0 = Yt1 + Yt1;
         const T Y2 = fm(Y0, Y0, Y1 * Y1);
         const T Yn = fm(Y0, nr, Y1 * nt);
         const T in2 = rcp(n2);
-        const T b = Yn * Yn * in2;
+        const T Yni = Yn * in2;
+        const T b = Yn * Yni;
         // Y_T^2 = |Y x n|^2 / n^2 directly, rather than Y^2 - Y_L^2, which
         // cancels for near-longitudinal propagation
         const T cz = fm(Y0, nt, -(Y1 * nr));
@@ -510,34 +517,40 @@ __device__ __forceinline__ bool ray_rhs(const GridDev<T> &g, const RayConst &rc,
         const T mY2 = ma;            // d mu^2 / d Y^2 at fixed b
         const T mb = mba - ma;       // d mu^2 / d b at fixed Y^2
         G = fm(X, mX, fm(Y2, mY2, fm(b, mb, -n2)));
-        // dH/dn = n - mb/2 db/dn, db/dn = 2 Yn Y/n2 - 2 Yn^2 n / n2^2
-        // (Yn^2 / n2^2 = b / n2)
-        const T c1 = mb * Yn * in2;
-        const T c2p = fm(mb * b, in2, T(1));
+        // dH/dn = n - mb/2 db/dn, db/dn = 2 Yn Y/n2 - 2 Yn^2 n / n2^2:
+        // n (1 + mb Yn^2 / n2^2) - mb (Yn / n2) Y
+        const T c1 = mb * Yni;
+        const T c2p = fm(c1, Yni, T(1));
         Hn0 = fm(nr, c2p, -(c1 * Y0));
         Hn1 = fm(nt, c2p, -(c1 * Y1));
         Hn2 = np * c2p;
         // dH/dq = -1/2 (mX dX/dq + mY2 dY^2/dq + mb db/dq); with dY/dr = -3Y/r,
-        // dY^2/dr = -6 Y^2 / r and db/dr = -6 b / r
-        const T dY2t = T(2) * fm(Y0, Yt0, Y1 * Yt1);
-        const T tYn = T(2) * Yn * in2;
-        const T dbt = tYn * fm(Yt0, nr, Yt1 * nt);
-        Hr = fm(T(-0.5) * mX, Xr, T(3) * ir * fm(mY2, Y2, mb * b));
-        Hth = T(-0.5) * fm(mX, Xth, fm(mY2, dY2t, mb * dbt));
-        Hph = T(-0.5) * (mX * Xph);
+        // dY^2/dr = -6 Y^2 / r and db/dr = -6 b / r.  Along th:
+        // -1/2 dY^2/dth = -(Y_r (-2 Y_th) + Y_th Y_r / 2) = 3 Y_th dY_th/dth,
+        // -1/2 db/dth = -(Yn / n2) (-2 Y_th n_r + dY_th/dth n_th)
+        const T sX = T(-0.5) * mX * inv_f2;
+        const T hY2t = T(3) * (Y1 * Yt1);
+        const T hbt = -Yni * fm(T(-2) * Y1, nr, Yt1 * nt);
+        Hr = fm(sX, Fr, T(3) * ir * fm(mY2, Y2, mb * b));
+        Hth = fm(sX, Fth, fm(mY2, hY2t, mb * hbt));
+        Hph = sX * Fph;
     }
+    // eq. (1): dx/dP' = -(dH/dn) / G and dn/dP' = (dH/dx) / G in the
+    // spherical frame, with the frame terms of n
     const T iG = rcp(G);
-    const T rdot = -Hn0 * iG;
-    const T thdot = -Hn1 * iG * ir;
-    const T phdot = -Hn2 * iG * irs;
-    const T stp = st * phdot, rtd = rr * thdot, rctp = rr * ct * phdot;
+    const T miG = -iG;
+    const T rdot = Hn0 * miG;
+    const T thdot = Hn1 * (miG * ir);
+    const T phdot = Hn2 * (miG * irs);
+    const T A = np * phdot;          // n_ph dph/dP'
+    const T B = rr * thdot;          // r dth/dP'
     dy[0] = double(rdot);
     dy[1] = double(thdot);
     dy[2] = double(phdot);
-    dy[3] = double(fm(Hr, iG, fm(nt, thdot, np * stp)));
-    dy[4] = double(fm(Hth, iG, fm(-nt, rdot, np * rctp)) * ir);
-    dy[5] = double(fm(Hph, iG, fm(-np * st, rdot, -(np * rr * ct * thdot))) * irs);
-    dy[6] = double(fm(nr, rdot, fm(nt, rtd, np * rr * stp)));
+    dy[3] = double(fm(Hr, iG, fm(nt, thdot, A * st)));
+    dy[4] = double(fm(Hth, iG, fm(-nt, rdot, A * (rr * ct))) * ir);
+    dy[5] = double(fm(Hph, iG, -(np * fm(st, rdot, ct * B))) * irs);
+    dy[6] = double(fm(nr, rdot, fm(nt, B, A * rst)));
     return isfinite(double(G)) && G != T(0);
 }
 
