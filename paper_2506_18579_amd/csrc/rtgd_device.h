@@ -230,8 +230,27 @@ template <int N>
 __device__ __forceinline__ float row_bcast(float v) { return dpp<0x150 + N>(v); }
 constexpr int kQuadXor1 = 0xB1;          // quad_perm(1, 0, 3, 2): lane ^ 1
 constexpr int kQuadXor2 = 0x4E;          // quad_perm(2, 3, 0, 1): lane ^ 2
-constexpr int kRowMirror = 0x140;        // lane i <- lane 15 - i within 16
-constexpr int kRowHalfMirror = 0x141;    // lane i <- lane 7 - i within 8
+// Per-lane choice between two values by a lane mask m (all ones or all
+// zeros) held in a VGPR: bitwise (b & m) | (a & ~m), one v_bfi_b32 per 32
+// bits, so that lane-dependent choices need no SGPR lane masks.
+__device__ __forceinline__ unsigned bfi(unsigned m, unsigned b, unsigned a)
+{
+    unsigned d;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(d) : "v"(m), "v"(b), "v"(a));
+    return d;
+}
+__device__ __forceinline__ double pick(unsigned m, double a, double b)
+{
+    const unsigned lo = bfi(m, unsigned(__double2loint(b)), unsigned(__double2loint(a)));
+    const unsigned hi = bfi(m, unsigned(__double2hiint(b)), unsigned(__double2hiint(a)));
+    return __hiloint2double(int(hi), int(lo));
+}
+__device__ __forceinline__ float pick(unsigned m, float a, float b)
+{
+    return __uint_as_float(bfi(m, __float_as_uint(b), __float_as_uint(a)));
+}
+constexpr int kRowRor8 = 0x128;          // lane i <- lane (i + 8) mod 16 within 16
+constexpr int kRowRor4 = 0x124;          // lane i <- lane (i + 4) mod 16 within 16
 
 // The grid lives in global memory; saying so (address space 1) lets the
 // compiler use global loads, which do not share a wait counter with the
@@ -250,7 +269,7 @@ __device__ __forceinline__ void col_load(gptr<T> p, T u[4])
 // Contraction order, shared by every kernel variant so that all give the
 // same rounded result: per column, heights in a fused chain (value and
 // d/dh); per latitude row, the four weighted columns as
-// (col0 + col1) + (col2 + col3); over rows, (row0 + row3) + (row1 + row2).
+// (col0 + col1) + (col2 + col3); over rows, (row0 + row2) + (row1 + row3).
 template <typename T>
 __device__ __forceinline__ void col_contract(const T u[4], const T wh[4], const T dwh[4], T &cv, T &dcv)
 {
@@ -272,7 +291,17 @@ struct StencilCache {
     T u[NA][NA][4];
     T uref;                   // node (1, 1, 1), the mixed path's reference
     Piece<T> pa, pb;          // LANES = 16: weights of this lane's a and b
+    unsigned m1, m2, m3;      // LANES = 16: all ones where lane & 3 is 1, 2, 3
     __device__ void clear() { il = -1; jl = -1; kh = -1; }
+    __device__ void set_masks(int lane)
+    {
+        m1 = (lane & 3) == 1 ? ~0u : 0u;
+        m2 = (lane & 3) == 2 ? ~0u : 0u;
+        m3 = (lane & 3) == 3 ? ~0u : 0u;
+        // opaque to the compiler from here on: it would turn pick() back
+        // into selects on SGPR lane masks, which crowd the SGPRs
+        asm volatile("" : "+v"(m1), "+v"(m2), "+v"(m3));
+    }
 };
 
 // f_N^2 (MHz^2, returned in FP64) and its partials d/dr, d/dtheta, d/dphi
@@ -370,10 +399,10 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
             plo[a] = s1 * wl[a];
             phh[a] = s2 * wl[a];
         }
-        v = (pv[0] + pv[3]) + (pv[1] + pv[2]);
-        glat = (pla[0] + pla[3]) + (pla[1] + pla[2]);
-        glon = (plo[0] + plo[3]) + (plo[1] + plo[2]);
-        gh = (phh[0] + phh[3]) + (phh[1] + phh[2]);
+        v = (pv[0] + pv[2]) + (pv[1] + pv[3]);
+        glat = (pla[0] + pla[2]) + (pla[1] + pla[3]);
+        glon = (plo[0] + plo[2]) + (plo[1] + plo[3]);
+        gh = (phh[0] + phh[2]) + (phh[1] + phh[3]);
     } else {
         T wo, dwo, wl, dwl, w1, dw1;
         eval_piece<T, IP>(sc.pb, T(so_), wo, dwo);
@@ -401,17 +430,21 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
         const T s0 = t0 + dpp<kQuadXor2>(t0);
         const T s1 = t1 + dpp<kQuadXor2>(t1);
         const T s2 = t2 + dpp<kQuadXor2>(t2);
-        T pv = s0 * wl, pla = s0 * dwl, plo = s1 * wl, phh = s2 * wl;
-        // across the row (lat offsets a): mirror pairs a with 3 - a, the half
-        // mirror then pairs (a, 3 - a) with (1 - a, 2 + a)
-        pv = pv + dpp<kRowMirror>(pv);
-        pla = pla + dpp<kRowMirror>(pla);
-        plo = plo + dpp<kRowMirror>(plo);
-        phh = phh + dpp<kRowMirror>(phh);
-        v = pv + dpp<kRowHalfMirror>(pv);
-        glat = pla + dpp<kRowHalfMirror>(pla);
-        glon = plo + dpp<kRowHalfMirror>(plo);
-        gh = phh + dpp<kRowHalfMirror>(phh);
+        // The four lanes of a quad now hold the same sums; lane b of each
+        // quad takes one of the four row products, q = b: the value s0 wl,
+        // d/dlat s0 dwl, d/dlon s1 wl, d/dh s2 wl, and sums it over the lat
+        // offsets a across the row: rotating by 8 lanes pairs a with a + 2,
+        // then by 4 pairs (a, a + 2) with (a + 1, a + 3).  Lane q of the row
+        // then holds quantity q, which the row broadcasts.
+        const T lhs = pick(sc.m3, pick(sc.m2, s0, s1), s2);
+        const T rhs = pick(sc.m1, wl, dwl);
+        T p = lhs * rhs;
+        p = p + dpp<kRowRor8>(p);
+        p = p + dpp<kRowRor4>(p);
+        v = row_bcast<0>(p);
+        glat = row_bcast<1>(p);
+        glon = row_bcast<2>(p);
+        gh = row_bcast<3>(p);
     }
     // index space -> physical: t_h = (r - R - h0)/dh,
     // t_lat = (90 - theta deg - lat0)/dlat, t_lon = (phi deg - lon0)/dlon

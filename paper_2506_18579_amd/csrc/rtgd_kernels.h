@@ -399,15 +399,18 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParam
             }
         }
     }
-    int status = -1;
     // y[i] * 0 is NaN exactly when y[i] is infinite or NaN, else +-0
     double z = L.y[0] * 0.0;
 #pragma unroll
     for (int i = 1; i < 7; ++i) z = fm(L.y[i], 0.0, z);
     const bool finite = ok && z == 0.0;
-    if (!finite) {
-        status = kNumeric;
-    } else if (h < P.floor_h && L.y[3] < 0.0) {
+    const bool below = h < P.floor_h && L.y[3] < 0.0;
+    // in order of precedence: NUMERIC, below the grid bottom, ESCAPE,
+    // MAX_PATH; the common outcome (-1) by selects, without branches
+    int status = (L.gp >= P.max_group || L.steps >= P.max_steps) ? kMaxPath : -1;
+    status = h >= P.exit_h ? kEscape : status;
+    status = finite ? status : kNumeric;
+    if (finite && below) {
         // below the grid bottom and descending: a ground return (k_finish
         // follows the vacuum line) unless the line misses the Earth
         double xd, c;
@@ -418,12 +421,8 @@ __device__ __forceinline__ int advance(const TraceParams<T> &P, const TraceParam
             L = graze_back(Pp, ray, L, write);
             return -1;
         }
-    } else if (h >= P.exit_h) {
-        status = kEscape;
-    } else if (L.gp >= P.max_group || L.steps >= P.max_steps) {
-        status = kMaxPath;
     }
-    if (status != kNumeric && h > L.apogee) L.apogee = h;
+    L.apogee = (status != kNumeric && h > L.apogee) ? h : L.apogee;
     if (P.traj_stride > 0 && write && (L.steps % P.traj_stride == 0 || status >= 0)) put_traj(P, ray, L);
     return status;
 }
@@ -464,6 +463,7 @@ __device__ __forceinline__ void run_rows(const TraceParams<T> &P, const TracePar
     sc.clear();
     sc.pa = piece<T, IP>((lane >> 2) & 3);
     sc.pb = piece<T, IP>(lane & 3);
+    sc.set_masks(lane);
     unsigned long long nsteps = 0;
     for (;;) {
         if (__ballot(ray >= 0) == 0ull) break;
@@ -760,6 +760,7 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
     sc.clear();
     sc.pa = piece<T, IP>((lane >> 2) & 3);
     sc.pb = piece<T, IP>(lane & 3);
+    sc.set_masks(lane);
     int ray = -1;
     Lane L;
     bool closing = false;
