@@ -375,8 +375,16 @@ void fill_grid_dev(const rt_grid *grid, GridDev<T> &g)
 {
     const rt_grid_geom &q = grid->geom;
     g.n_lat = q.n_lat; g.n_lon = q.n_lon; g.n_h = q.n_h;
-    g.lat0 = q.lat0_deg; g.lon0 = q.lon0_deg; g.h0 = q.h0_km;
-    g.inv_dlat = 1.0 / q.dlat_deg; g.inv_dlon = 1.0 / q.dlon_deg; g.inv_dh = 1.0 / q.dh_km;
+    g.h0 = q.h0_km;
+    // t_lat = (90 - th deg - lat0) / dlat, t_lon = (ph deg - lon0) / dlon,
+    // t_h = (h - h0) / dh as affine maps of th, ph (rad) and h
+    const double inv_dlat = 1.0 / q.dlat_deg, inv_dlon = 1.0 / q.dlon_deg;
+    g.lat_a = -kRad2Deg * inv_dlat;
+    g.lat_b = (90.0 - q.lat0_deg) * inv_dlat;
+    g.lon_a = kRad2Deg * inv_dlon;
+    g.lon_b = -q.lon0_deg * inv_dlon;
+    g.inv_dh = 1.0 / q.dh_km;
+    g.h_b = -q.h0_km * g.inv_dh;
     g.kmax_lat = double(q.n_lat - 3); g.kmax_lon = double(q.n_lon - 3); g.kmax_h = double(q.n_h - 3);
     g.R = q.earth_radius_km;
 }

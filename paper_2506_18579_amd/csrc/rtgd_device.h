@@ -40,8 +40,11 @@ enum RayStatus : int32_t { kGround = 0, kEscape = 1, kMaxPath = 2, kNumeric = 3 
 template <typename T>
 struct GridDev {
     int32_t n_lat, n_lon, n_h;
-    double lat0, lon0, h0;      // first node (deg, deg, km)
-    double inv_dlat, inv_dlon, inv_dh;
+    double h0;                  // grid bottom (km)
+    // index coordinates as affine maps: t_lat = lat_a th + lat_b (th the
+    // colatitude, rad), t_lon = lon_a ph + lon_b (ph the longitude, rad),
+    // t_h = inv_dh h + h_b (h the height, km)
+    double lat_a, lat_b, lon_a, lon_b, inv_dh, h_b;
     double kmax_lat, kmax_lon, kmax_h;   // last cell of each axis: n - 3
     double R;                   // Earth radius, km
 };
@@ -328,9 +331,9 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
     // (selects, no branches)
     double sl_, so_, sh_;
     bool cl, co, ch;
-    const int il = locate((fm(-th, kRad2Deg, 90.0) - g.lat0) * g.inv_dlat, g.kmax_lat, sl_, cl);
-    const int jl = locate((ph * kRad2Deg - g.lon0) * g.inv_dlon, g.kmax_lon, so_, co);
-    const int kh = locate((h - g.h0) * g.inv_dh, g.kmax_h, sh_, ch);
+    const int il = locate(fm(th, g.lat_a, g.lat_b), g.kmax_lat, sl_, cl);
+    const int jl = locate(fm(ph, g.lon_a, g.lon_b), g.kmax_lon, so_, co);
+    const int kh = locate(fm(h, g.inv_dh, g.h_b), g.kmax_h, sh_, ch);
 
     const size_t nh = size_t(g.n_h);
     const size_t row = size_t(g.n_lon) * nh;
@@ -446,15 +449,15 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
         glon = row_bcast<2>(p);
         gh = row_bcast<3>(p);
     }
-    // index space -> physical: t_h = (r - R - h0)/dh,
-    // t_lat = (90 - theta deg - lat0)/dlat, t_lon = (phi deg - lon0)/dlon
+    // index space -> physical: dt_h/dr = 1/dh, dt_lat/dth = lat_a,
+    // dt_lon/dph = lon_a
     // FP32: the base node value plus the contracted differences, summed in
     // FP64 so that 1 - X keeps its relative accuracy where X -> 1
     if constexpr (sizeof(T) == 4) F = double(v) + double(uref);
     else F = v;
     Fr = ch ? T(0) : gh * T(g.inv_dh);
-    Fth = cl ? T(0) : glat * T(-kRad2Deg * g.inv_dlat);
-    Fph = co ? T(0) : glon * T(kRad2Deg * g.inv_dlon);
+    Fth = cl ? T(0) : glat * T(g.lat_a);
+    Fph = co ? T(0) : glon * T(g.lon_a);
 }
 
 // Appleton-Hartree partial derivatives of mu^2 with respect to X,
@@ -627,7 +630,9 @@ __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc
     bool ok = true;
     if (!(fabs(y[1] - an.th) <= kAnchorMove)) an = make_anchor(y[1]);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) { t[i] = y[i]; acc[i] = 0.0; }
+    // acc starts at -0: 1 * k + (-0) is k exactly (also for k = +-0), so
+    // the unrolled form may take k itself at the first stage
+    for (int i = 0; i < 7; ++i) { t[i] = y[i]; acc[i] = -0.0; }
     auto stage_body = [&](int stage) {
         const double d = t[1] - an.th;
         double st, ct;
@@ -647,7 +652,7 @@ __device__ __forceinline__ bool rk4_step(const GridDev<T> &g, const RayConst &rc
         const double c = (stage == 2) ? h : 0.5 * h;
 #pragma unroll
         for (int i = 0; i < 7; ++i) {
-            acc[i] = fm(wgt, k[i], acc[i]);
+            acc[i] = (UNROLL && stage == 0) ? k[i] : fm(wgt, k[i], acc[i]);
             t[i] = fm(c, k[i], y[i]);
         }
     };
