@@ -131,6 +131,7 @@ def roofline(res, modes, run, wl, precision):
     per_kernel = {
         "k_start+k_trace": {"ray_steps": one + promo, "ray_steps_one_lane": one,
                             "ray_steps_promotion_rows": promo, "ms": tms,
+                            "one_lane_occupancy": one / max(1, 64 * res["one_lane_wave_iters"]),
                             "frac": (one + promo) * avg / (tms * 1e-3) / 1e12 / peak},
         "k_tail+k_finish": {"ray_steps": rows, "ms": lms,
                             "frac": rows * avg / (lms * 1e-3) / 1e12 / peak if lms > 0 else None}}

@@ -204,6 +204,11 @@ typedef struct {
      * ray-start and one-lane kernels, then of the tail and finish kernels */
     int64_t steps_one_lane, steps_promoted, steps_rows;
     double trace_ms, tail_ms;
+    /* out (rt_trace only): iterations of the one-lane waves that stepped at
+     * least one ray, summed over the waves; steps_one_lane / (64 x this) is
+     * the share of lane slots that held a ray (the one-lane kernel's lane
+     * occupancy) */
+    int64_t one_lane_wave_iters;
 } rt_results;
 
 /* Create a context on HIP device `device` issuing work on `hip_stream`
@@ -380,7 +385,8 @@ void rt_plan_destroy(rt_plan *plan);
  * candidate setting (tail_threshold in {-2, -1, 8 and 16 rays per CU} x
  * waves_per_simd in {1, 2} x ray_order in {index, strided, mode-sorted};
  * then, on top of
- * the fastest of those unless it is the in-wave switch, promote_waves in
+ * the fastest of those other than the in-wave switch (promotion does not
+ * combine with it), promote_waves in
  * {16, 32, 64} with promote_age -1, each with cu_layout 2 and 1; the first
  * stage runs without promotion; one untimed run, then the median device
  * time of three), times the fastest and the library defaults again, seven

@@ -451,7 +451,8 @@ struct Counters {
     // RK4 ray-steps by phase: one lane per ray, promotion rows, 16-lane rows
     // after the hand-off (or of the in-wave switch)
     unsigned long long phase_steps[3];
-    int32_t pad2[10];
+    unsigned long long wave_iters;   // one-lane wave iterations that stepped a ray
+    int32_t pad2[8];
 };
 static_assert(sizeof(Counters) % 64 == 0, "counters fill whole cache lines");
 
@@ -636,6 +637,7 @@ void fill_params(const TraceJob &job, const Layout &lay, TraceParams<T> &P, char
     P.promo_err = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, promo_err));
     P.unfinished = reinterpret_cast<int32_t *>(cnt + offsetof(Counters, unfinished));
     P.phase_steps = reinterpret_cast<unsigned long long *>(cnt + offsetof(Counters, phase_steps));
+    P.wave_iters = reinterpret_cast<unsigned long long *>(cnt + offsetof(Counters, wave_iters));
     P.promo_ids = reinterpret_cast<int32_t *>(dev + lay.ids);
     // Longest wait of an idle promotion wave while one-lane waves still run,
     // in wall-clock ticks: far above the one-lane waves' worst case (every
@@ -861,6 +863,7 @@ rt_status trace_results(rt_ctx *ctx, const TraceJob &job, const char *host, rt_r
     res->steps_one_lane = int64_t(hc.phase_steps[0]);
     res->steps_promoted = int64_t(hc.phase_steps[1]);
     res->steps_rows = int64_t(hc.phase_steps[2]);
+    res->one_lane_wave_iters = int64_t(hc.wave_iters);
     rt_status st = launch_error(ctx, hc);
     if (st != RT_OK) return st;
     return hc.trunc ? RT_W_TRAJ_TRUNCATED : RT_OK;
@@ -871,6 +874,7 @@ void clear_results(rt_results *res)
     res->total_steps = 0;
     res->kernel_ms = res->trace_ms = res->tail_ms = 0.0;
     res->steps_one_lane = res->steps_promoted = res->steps_rows = 0;
+    res->one_lane_wave_iters = 0;
 }
 
 }  // namespace
@@ -1638,6 +1642,8 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     o.cu_layout = 0;
     st = time_opts(o, inf.default_ms);
     o.promote_waves = -1;     // the first stage runs without promotion
+    double best_h = 1e300;    // the best with a launch-wide hand-off or none
+    TuneVal bh{0, 0, 0, 0, 0, 0};
     for (int oc : occs) {
         for (int tl : tails) {
             for (int od : orders) {
@@ -1649,15 +1655,16 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
                 st = time_opts(o, ms);
                 ++inf.n_candidates;
                 if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od, -1, 0, 0}; }
+                if (st == RT_OK && tl != -2 && ms < best_h) { best_h = ms; bh = TuneVal{tl, oc, od, -1, 0, 0}; }
             }
         }
     }
-    // then promotion on top of the best of those (not with the in-wave
-    // switch), in both work-group layouts
+    // then promotion on top of the best of those without the in-wave switch
+    // (promotion does not combine with it), in both work-group layouts
     const int promos[3][2] = {{16, -1}, {32, -1}, {64, -1}};
     const int layouts[2] = {2, 1};
-    if (bv.tail_threshold != -2) {
-        const TuneVal base_v = bv;
+    if (best_h < 1e300) {
+        const TuneVal base_v = bh;
         for (const auto &pr : promos) {
             for (int lay : layouts) {
                 if (st != RT_OK) break;

@@ -89,7 +89,8 @@ struct TraceParams {
     int32_t *producers_alive;  // one-lane waves still running
     int32_t *promo_err;        // waits that timed out (reported as a launch error)
     int32_t *unfinished;       // rays k_finish found without a final status (a launch error)
-    unsigned long long *phase_steps;   // RK4 ray-steps run one lane per ray, on promotion
+    unsigned long long *phase_steps;
+    unsigned long long *wave_iters;  // one-lane wave iterations that stepped a ray   // RK4 ray-steps run one lane per ray, on promotion
                                        // rows, on 16-lane rows after the hand-off (or the
                                        // in-wave switch)
     int64_t idle_ticks;        // wall-clock bound of an idle promotion wave's wait
@@ -609,7 +610,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
     Lane L;
     StencilCache<T, 1> sc;
     sc.clear();
-    unsigned long long nsteps = 0;
+    unsigned long long nsteps = 0, iters = 0;
     for (int iter = 0;; ++iter) {
         bool need = (ray == -1);
         if (__ballot(need)) {
@@ -663,6 +664,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
         }
         // every 32nd iteration: an attempt costs atomics on shared counters
         if (P.promote_cap > 0 && (iter & 31) == 0) promote(P, ray, L, lane);
+        iters += __ballot(ray >= 0) != 0ull ? 1u : 0u;
         int st = -1;
         if (ray >= 0) {
             ++nsteps;
@@ -676,6 +678,7 @@ __device__ __forceinline__ void trace_body(const TraceParams<T> &P, const TraceP
         if (lane == 0 && fin && P.handoff_threshold > 0) atomicSub(P.live, __popcll(fin));
     }
     add_wave_steps(P.phase_steps, nsteps);
+    if (lane == 0 && iters) atomicAdd(P.wave_iters, iters);
     // Release: the wave's earlier tickets (promo_push) and records are
     // visible to any promotion wave that reads the decremented count with
     // acquire.  The fence covers every lane's operations (a wave waits on

@@ -64,7 +64,8 @@ def main():
         print(json.dumps({"rep": i, "workload": wl.name, "precision": a.precision,
                           "ray_steps": out["total_steps"], "kernel_ms": out["kernel_ms"],
                           "trace_ms": out["trace_ms"], "tail_ms": out["tail_ms"],
-                          "phase_steps": out["phase_steps"]}),
+                          "phase_steps": out["phase_steps"],
+                          "one_lane_occupancy": out["phase_steps"][0] / max(1, 64 * out["one_lane_wave_iters"])}),
               flush=True)
     grid.close()
     ctx.close()

@@ -76,7 +76,8 @@ class Results(ctypes.Structure):
                 ("traj", _DP), ("traj_count", _IP), ("total_steps", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("steps_one_lane", ctypes.c_int64),
                 ("steps_promoted", ctypes.c_int64), ("steps_rows", ctypes.c_int64),
-                ("trace_ms", ctypes.c_double), ("tail_ms", ctypes.c_double)]
+                ("trace_ms", ctypes.c_double), ("tail_ms", ctypes.c_double),
+                ("one_lane_wave_iters", ctypes.c_int64)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -330,8 +331,9 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
     Returns a dict of per-ray arrays (numpy on the host, or torch tensors on
     the device with device_results=True; pass `out` to reuse device
     tensors), plus total_steps, kernel_ms and how the launch ran:
-    phase_steps (one lane, promotion rows, 16-lane rows), trace_ms and
-    tail_ms."""
+    phase_steps (one lane, promotion rows, 16-lane rows), trace_ms,
+    tail_ms and one_lane_wave_iters (one-lane wave iterations that stepped a
+    ray)."""
     fa = FanArgs(fan)
     n = ctypes.c_int64(0)
     st = lib().rt_fan_count(ctypes.byref(fa.s), ctypes.byref(n))
@@ -374,6 +376,7 @@ def trace(ctx: Context, grid: Grid, fan, step_km=1.0, max_group_km=4000.0, exit_
     res["total_steps"] = int(r.total_steps)
     res["kernel_ms"] = float(r.kernel_ms)
     res["phase_steps"] = (int(r.steps_one_lane), int(r.steps_promoted), int(r.steps_rows))
+    res["one_lane_wave_iters"] = int(r.one_lane_wave_iters)
     res["trace_ms"] = float(r.trace_ms)
     res["tail_ms"] = float(r.tail_ms)
     res["truncated"] = st == RT_W_TRAJ_TRUNCATED

@@ -187,6 +187,9 @@ def test_ionogram_every_ray(rt, ctx, ionogram_sweep, ionogram_sweep_oracle):
     rep = compare(g, o, wl.fan.expand(), tr)
     assert g["total_steps"] == o["total_steps"] == sum(g["phase_steps"])
     assert g["phase_steps"][1] > 0 and g["phase_steps"][2] > 0    # promotion and tail both ran
+    # lane occupancy of the one-lane waves: each iteration steps at most 64 rays
+    assert 0 < g["phase_steps"][0] <= 64 * g["one_lane_wave_iters"] < 64 * g["phase_steps"][0]
+    print("ionogram every ray: one-lane occupancy", g["phase_steps"][0] / (64 * g["one_lane_wave_iters"]))
     print("ionogram every ray: within 1e-9", rep["n_within"], "of", rep["n"], "worst", rep["worst_rel"],
           "median", rep["median_rel"], "ill-conditioned", rep["ill_conditioned"])
     assert len(rep["ill_conditioned"]) <= 50

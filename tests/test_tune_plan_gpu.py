@@ -52,7 +52,7 @@ def test_autotune_choice_is_cached_and_result_neutral(rt, ctx, grid, wl, tmp_pat
     kw = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km)
     rt.tune_cache_clear()
     t = rt.autotune(ctx, grid, fan, precision="mixed", **kw)
-    assert not t["from_cache"] and t["n_candidates"] in (24, 30)   # + promotion x layout unless in-wave wins
+    assert not t["from_cache"] and t["n_candidates"] == 30   # 24 first-stage + 3 promotion x 2 layouts
     assert t["tail_threshold"] in (-2, -1, 0) or t["tail_threshold"] % 8 == 0
     assert t["ray_order"] in (0, 1, 2, 3) and t["waves_per_simd"] in (0, 1, 2)
     assert 0 < t["best_ms"] <= t["default_ms"]
