@@ -33,16 +33,16 @@ FLOPS_PER_STEP = {"O": 3346.0, "X": 3278.0, "iso": 2666.0}
 PEAK_FP64_VALU_TFLOPS = 78.6      # MI355X vector FP64 (256 CU x 2.4 GHz x 128)
 PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 
-# HBM bytes of one FP64 ionogram launch (k_start, k_trace, k_tail and
-# k_finish; the autotuned setting: hand-off at 4096 rays, 32 promotion waves
-# for trapped and grazing rays) from rocprofv3: FETCH_SIZE x 2.000 +
-# WRITE_SIZE x 1.000 (factors from a 1 GiB device copy in the same runs).
-# Valid only for the device sources (per-step arithmetic and trace kernels)
-# with these hashes; otherwise reported as null.
-TRAFFIC_BYTES = (76280 + 48017) * 1024
+# HBM bytes of one ionogram launch (k_start, k_trace, k_tail and k_finish;
+# the autotuned settings: hand-off at 4096 rays, 32 promotion waves for
+# trapped and grazing rays) from rocprofv3, per precision: FETCH_SIZE x 2.000
+# + WRITE_SIZE x 1.000 KiB (factors from a 1 GiB device copy in the same
+# runs).  Valid only for the device sources (per-step arithmetic and trace
+# kernels) with these hashes; otherwise reported as null.
+TRAFFIC_BYTES = {"fp64": (76865 + 48780) * 1024, "mixed": (69787 + 48222) * 1024}
 TRAFFIC_SOURCES = {
-    "rtgd_device.h": "fc2671d864d65019d61ee6dcdc3f5df412c22267d5495bb45054fd1589ddab48",
-    "rtgd_kernels.h": "3700c5caf5f3c2d5f2c992a4bc176ea4ea361702d9c0259e38cdf231dc9335a1",
+    "rtgd_device.h": "5c798a8a4e52c5ea44e1ca2a8b70292d9f93363db7230055e444e88592069108",
+    "rtgd_kernels.h": "c7f65134b9022de3358b345487ef4b0f793b8f6955b25e6e5381ee17ba1451a3",
 }
 
 
@@ -51,14 +51,14 @@ TUNED_KNOBS = ("tail_threshold", "waves_per_simd", "ray_order", "promote_waves",
                "cu_layout")
 
 
-def measured_traffic():
+def measured_traffic(precision):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2506_18579_amd", "csrc")
     for name, digest in TRAFFIC_SOURCES.items():
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
-    return TRAFFIC_BYTES
+    return TRAFFIC_BYTES[precision]
 
 
 def parse():
@@ -137,7 +137,7 @@ def roofline(res, modes, run, wl, precision):
                             "frac": rows * avg / (lms * 1e-3) / 1e12 / peak if lms > 0 else None}}
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic() if precision == "fp64" else None,
+            "traffic": measured_traffic(precision),
             "kernel": "trace launch: k_start + k_trace + k_tail + k_finish (" + precision + ")",
             "kernel_ms_avg": kms, "flops_per_launch": flops, "flops_per_ray_step_avg": avg,
             "flops_per_ray_step": FLOPS_PER_STEP,
