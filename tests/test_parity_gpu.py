@@ -403,6 +403,8 @@ def test_promotion_is_bit_identical(rt, ctx, precision):
                            dict(promote_waves=4, promote_age=-1, tail_threshold=-1))]
     finally:
         grid.close()
+    for r in runs:      # every ray finished (a ray no kernel finished keeps status -1)
+        assert (r["status"] >= 0).all()
     for k in ("group_km", "phase_km", "range_km", "az_dev_deg", "apogee_km", "land_lat_deg",
               "land_lon_deg", "status", "n_steps"):
         for other in runs[1:]:
