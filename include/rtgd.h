@@ -317,10 +317,10 @@ typedef struct rt_server rt_server;
 
 typedef struct {
     int64_t mem_budget_bytes;  /* output arena; 0 = 256 MiB                    */
-    int32_t n_slots;           /* concurrent launches (streams); 0 = 4, <= 64    */
+    int32_t n_slots;           /* concurrent launches (streams); 0 = 2, <= 64    */
     int32_t max_batch_requests;/* requests per launch; 0 = 256                   */
     int32_t max_batch_rays;    /* rays per launch (a larger single request still
-                                  runs alone); 0 = 262144                        */
+                                  runs alone); 0 = 1048576                       */
     int32_t reserved;          /* must be 0                                      */
 } rt_server_opts;
 

@@ -1136,7 +1136,7 @@ struct rt_server {
     std::deque<rt_request_info> done;
     int64_t next_id = 1;
     int max_batch_requests = 256;
-    int64_t max_batch_rays = 1 << 18;
+    int64_t max_batch_rays = 1 << 20;
 };
 
 namespace {
@@ -1229,7 +1229,11 @@ extern "C" rt_status rt_server_create(rt_ctx *ctx, const rt_server_opts *opts, r
     if (!ctx || !out) return RT_E_INVALID;
     *out = nullptr;
     int64_t budget = opts && opts->mem_budget_bytes > 0 ? opts->mem_budget_bytes : (int64_t(256) << 20);
-    int n_slots = opts && opts->n_slots > 0 ? opts->n_slots : 4;
+    // two slots: one launch runs its bulk while the other finishes its
+    // longest rays; with more, launches that each fill the GPU contend and
+    // stretch one another (measured on the serving mix and on back-to-back
+    // sweeps, as were the default batch limits)
+    int n_slots = opts && opts->n_slots > 0 ? opts->n_slots : 2;
     if (n_slots > 64) return fail(ctx, RT_E_INVALID, "at most 64 slots");
     if (opts && (opts->max_batch_requests < 0 || opts->max_batch_rays < 0))
         return fail(ctx, RT_E_INVALID, "negative batch limit");

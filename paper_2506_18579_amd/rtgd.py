@@ -439,11 +439,12 @@ def ionogram(ctx: Context, fan, res, range_km: float, max_points: int = 8):
 class Server:
     """Request server (rt_server_*): continuous batching of ray-fan
     requests (queued requests are launched together, as slots free up) over
-    `n_slots` streams with a device output arena of `mem_budget_bytes`.  submit() never blocks; poll() launches queued work
+    `n_slots` streams (0: the library default, 2) with a device output arena
+    of `mem_budget_bytes`.  submit() never blocks; poll() launches queued work
     and returns finished requests; fetch() copies a finished request's
     per-ray outputs out and frees its arena block."""
 
-    def __init__(self, ctx: Context, n_slots: int = 4, mem_budget_bytes: int = 256 << 20,
+    def __init__(self, ctx: Context, n_slots: int = 0, mem_budget_bytes: int = 256 << 20,
                  max_batch_requests: int = 0, max_batch_rays: int = 0):
         self.ctx = ctx
         self.h = ctypes.c_void_p()
