@@ -167,9 +167,7 @@ typedef struct {
                                one work-group per CU (an LDS reservation
                                keeps others off the CU), so the promotion
                                waves, the launch's last work-groups, have
-                               CUs to themselves; 0 = default: 2 for a
-                               single-request launch (rt_trace, a plan, a
-                               server batch of one), else 1                */
+                               CUs to themselves; 0 = default (2)        */
 } rt_trace_opts;
 
 /* Per-ray outputs, arrays of N_r = rt_fan_count() elements, owned by the

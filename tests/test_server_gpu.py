@@ -91,18 +91,21 @@ def test_each_result_same_alone_and_in_mix(rt, ctx, grids, precision):
         same(mixed[rid], alone)
 
 
+@pytest.mark.parametrize("cu_layout", [0, 1])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_large_merged_launch_matches_alone(rt, ctx, grids, precision):
+def test_large_merged_launch_matches_alone(rt, ctx, grids, precision, cu_layout):
     """Three 6,000-ray requests queued behind one slot are launched together
-    (18,000 rays: enough for the default promotion waves, which a launch of
-    several requests runs beside two one-lane waves per SIMD where they fit).
+    (18,000 rays: enough for the default promotion waves), in the default
+    grouped layout (four-wave work-groups, one per CU) and in one-wave
+    work-groups (where the FP32 kernel holds two one-lane waves per SIMD).
     Every result equals, bit for bit, its fan traced alone (6,000 rays: no
     promotion)."""
     fans = [synth.Fan(30.0, 110.0, 0.0, np.linspace(5.0, 65.0, 60), np.linspace(-60.0, 60.0, 100),
                       np.array([f]), (m,)) for f, m in ((7.0, 1), (9.5, -1), (12.0, 1))]
     srv = rt.Server(ctx, n_slots=1, mem_budget_bytes=64 << 20)
     try:
-        ids = {srv.submit(grids[k % len(grids)], fan, **opts(precision)): k for k, fan in enumerate(fans)}
+        ids = {srv.submit(grids[k % len(grids)], fan, **opts(precision), cu_layout=cu_layout): k
+               for k, fan in enumerate(fans)}
         done = drain(srv, len(fans))
         got = {rid: srv.fetch(rid, done[rid]["n_rays"]) for rid in ids}
     finally:
