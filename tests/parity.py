@@ -25,8 +25,20 @@ import numpy as np
 
 LEN_KEYS = ("group_km", "phase_km", "range_km", "apogee_km")
 ANG_KEYS = ("az_dev_deg", "land_lat_deg", "land_lon_deg")
+# angles defined modulo 360 deg: the landing longitude is reported nearest the
+# transmitter's and the azimuth deviation in (-180, 180], and both choices
+# are ties where the landing point lies on the antipodal meridian or the
+# deviation is 180 deg, which a last-bit difference in atan2 decides either
+# way; their differences are compared modulo 360
+PERIODIC_KEYS = ("az_dev_deg", "land_lon_deg")
 NUMERIC = 3
 TOL_KM, TOL_DEG = 0.1, 0.001
+
+
+def diff(k, a, b):
+    """a - b for output k, periodic angles reduced to [-180, 180]."""
+    d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    return d - 360.0 * np.round(d / 360.0) if k in PERIODIC_KEYS else d
 
 
 def _scaled_err(g, o):
@@ -34,8 +46,8 @@ def _scaled_err(g, o):
     NUMERIC on both sides score 0 (their outputs are NaN)."""
     err = np.zeros(len(o["status"]))
     for k in LEN_KEYS + ANG_KEYS:
-        a, b = np.asarray(g[k], dtype=np.float64), np.asarray(o[k], dtype=np.float64)
-        err = np.maximum(err, np.abs(a - b) / np.maximum(np.abs(b), 1.0))
+        d = diff(k, g[k], o[k])
+        err = np.maximum(err, np.abs(d) / np.maximum(np.abs(np.asarray(o[k], dtype=np.float64)), 1.0))
     both_numeric = (np.asarray(g["status"]) == NUMERIC) & (np.asarray(o["status"]) == NUMERIC)
     err[both_numeric] = 0.0
     return np.where(np.isnan(err), np.inf, err)
@@ -111,7 +123,7 @@ def _mixed_ok(g, o, tol_km=TOL_KM, tol_deg=TOL_DEG):
     num = same & (o["status"] == NUMERIC)
     d_r = np.abs(g["range_km"] - o["range_km"])
     d_g = np.abs(g["group_km"] - o["group_km"])
-    d_a = np.abs(g["az_dev_deg"] - o["az_dev_deg"])
+    d_a = np.abs(diff("az_dev_deg", g["az_dev_deg"], o["az_dev_deg"]))
     close = (d_r <= tol_km) & (d_g <= tol_km) & (d_a <= tol_deg)
     return num | (same & close)
 
@@ -141,7 +153,7 @@ def classify_mixed(gpu, ora, rays, trace_oracle, gpu_idx=None, tol_km=TOL_KM, to
     same = (g["status"] == o["status"]) & (o["status"] != NUMERIC)
     stats = {}
     for k in ("group_km", "range_km", "az_dev_deg"):
-        d = np.abs(g[k] - o[k])
+        d = np.abs(diff(k, g[k], o[k]))
         for name, sel in (("within", ok & same), ("all", same)):
             v = d[sel]
             stats[f"{k}_max_{name}"] = float(v.max()) if v.size else 0.0
@@ -150,7 +162,7 @@ def classify_mixed(gpu, ora, rays, trace_oracle, gpu_idx=None, tol_km=TOL_KM, to
                   gpu_status=int(g["status"][k]), ora_status=int(o["status"][k]),
                   d_range=float(g["range_km"][k] - o["range_km"][k]),
                   d_group=float(g["group_km"][k] - o["group_km"][k]),
-                  d_az=float(g["az_dev_deg"][k] - o["az_dev_deg"][k])) for k in np.flatnonzero(fail)]
+                  d_az=float(diff("az_dev_deg", g["az_dev_deg"][k], o["az_dev_deg"][k]))) for k in np.flatnonzero(fail)]
     return dict(n=n, n_within=int(ok.sum()), n_ill=int(ill.sum()), n_fail=int(fail.sum()),
                 n_status_mismatch=int((g["status"] != o["status"]).sum()), failures=fails, **stats)
 
@@ -171,7 +183,7 @@ def error_stats(gpu, ora, gpu_idx=None):
     same &= np.asarray(ora["status"]) != 3
     out = {"n_compared": int(same.sum()), "n_status_mismatch": int((~same).sum())}
     for k in ("group_km", "range_km", "phase_km", "az_dev_deg", "apogee_km"):
-        d = np.asarray(gpu[k])[gpu_idx][same] - np.asarray(ora[k])[same]
+        d = diff(k, np.asarray(gpu[k])[gpu_idx][same], np.asarray(ora[k])[same])
         out[k] = {"max": float(np.abs(d).max()) if d.size else 0.0,
                   "rms": float(np.sqrt(np.mean(d ** 2))) if d.size else 0.0}
     return out

@@ -301,6 +301,34 @@ def test_rays_leaving_the_grid_box(rt, ctx, orc, aniso_wl, aniso_grid):
     compare(g, tr(*rays), rays, tr)
 
 
+def test_degenerate_launch_directions(rt, ctx, orc, aniso_wl, aniso_grid):
+    """Horizontal and vertical launches (elevation 0 and 90 deg, where the
+    azimuth only names the plane), azimuths on both sides of north and of
+    180 deg, O and X."""
+    fan = synth.Fan(30.0, 110.0, 0.0, np.array([0.0, 0.5, 89.5, 90.0]),
+                    np.array([0.0, 90.0, 179.99, 180.0, -90.0, 359.99]), np.array([6.0, 12.0]), (1, -1))
+    g = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan)
+    rays = fan.expand()
+    tr = oracle_tracer(orc, aniso_wl, fan)
+    compare(g, tr(*rays), rays, tr)
+
+
+def test_paths_over_the_pole(rt, ctx, orc, aniso_wl, aniso_grid):
+    """A transmitter 3 deg from the north pole with rays heading north: the
+    colatitude passes through zero (sin theta changes sign) on the way, far
+    outside the grid box, where the density is continued as a constant."""
+    fan = synth.Fan(87.0, 110.0, 0.0, np.array([3.0, 8.0, 15.0, 25.0]), np.array([0.0, 1.0, 30.0]),
+                    np.array([5.0, 9.0]), (1, -1))
+    g = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan)
+    rays = fan.expand()
+    tr = oracle_tracer(orc, aniso_wl, fan)
+    o = tr(*rays)
+    compare(g, o, rays, tr)
+    # some of these rays do cross the pole: their landing longitude differs
+    # from the transmitter's by more than 90 deg
+    assert np.any(np.abs(((o["land_lon_deg"] - 110.0) + 180.0) % 360.0 - 180.0) > 90.0)
+
+
 def test_empty_fan_is_a_noop(rt, ctx, iso_wl, iso_grid):
     fan = synth.Fan(30.0, 110.0, 0.0, np.array([]), np.array([0.0]), np.array([10.0]), (1,))
     g = gpu_trace(rt, ctx, iso_grid, iso_wl, fan)

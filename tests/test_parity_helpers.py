@@ -54,3 +54,16 @@ def test_mixed_classification(orc):
     assert rep["n_fail"] == 3 and sorted(f["ray"] for f in rep["failures"]) == [4, 6, 8]
     assert rep["n_within"] == rep["n"] - 3
     assert abs(rep["group_km_max_within"] - 0.05) < 1e-9
+
+
+def test_periodic_angles_compared_modulo_360(orc):
+    """The landing longitude and the azimuth deviation are angles: a result
+    that names the same angle another way (a landing point on the antipodal
+    meridian reported as lon + 360) is the same result."""
+    rays, tr, o = _setup(orc)
+    g = _copy(o)
+    g["land_lon_deg"][1] += 360.0           # the same longitude
+    g["az_dev_deg"][2] -= 360.0             # the same deviation
+    g["land_lon_deg"][4] += 360.0 + 1e-3    # another longitude
+    rep = classify_fp64(g, o, rays, tr)
+    assert [f["ray"] for f in rep["failures"]] == [4]
