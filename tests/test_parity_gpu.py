@@ -313,6 +313,18 @@ def test_degenerate_launch_directions(rt, ctx, orc, aniso_wl, aniso_grid):
     compare(g, tr(*rays), rays, tr)
 
 
+@pytest.mark.parametrize("tx_h_km", [12.5, 59.9])
+def test_elevated_transmitter(rt, ctx, orc, aniso_wl, aniso_grid, tx_h_km):
+    """A transmitter above the ground (an aircraft; one 100 m below the grid
+    bottom, so that the launch's vacuum segment is nearly empty)."""
+    fan = synth.Fan(30.0, 110.0, tx_h_km, np.array([0.0, 2.0, 10.0, 45.0]), np.array([0.0, 45.0, 135.0]),
+                    np.array([6.0, 12.0]), (1, -1))
+    g = gpu_trace(rt, ctx, aniso_grid, aniso_wl, fan)
+    rays = fan.expand()
+    tr = oracle_tracer(orc, aniso_wl, fan)
+    compare(g, tr(*rays), rays, tr)
+
+
 def test_paths_over_the_pole(rt, ctx, orc, aniso_wl, aniso_grid):
     """A transmitter 3 deg from the north pole with rays heading north: the
     colatitude passes through zero (sin theta changes sign) on the way, far
