@@ -325,6 +325,26 @@ def test_elevated_transmitter(rt, ctx, orc, aniso_wl, aniso_grid, tx_h_km):
     compare(g, tr(*rays), rays, tr)
 
 
+@pytest.mark.parametrize("B0", [0.0, synth.B0_DIPOLE_T])
+def test_smallest_grid(rt, ctx, orc, aniso_wl, B0):
+    """A grid of 4 x 5 x 6 nodes, the fewest an axis may have plus one and
+    two: every axis has one or two cells, so the weights are evaluated on the
+    edge cells' extended range s in [-1, 2] almost everywhere."""
+    geom = synth.GridGeom(4, 5, 6, 28.5, 1.0, 108.0, 1.0, 60.0, 90.0)
+    small = synth.ionosphere_grid(geom, 3, B0_T=B0)
+    wl = dataclasses.replace(aniso_wl, grid=small)
+    fan = synth.Fan(30.0, 110.0, 0.0, np.array([5.0, 20.0, 40.0, 70.0]), np.array([0.0, 90.0, 200.0]),
+                    np.array([4.0, 8.0]), (1, -1))
+    grid = rt.Grid(ctx, small)
+    try:
+        g = gpu_trace(rt, ctx, grid, wl, fan)
+    finally:
+        grid.close()
+    rays = fan.expand()
+    tr = oracle_tracer(orc, wl, fan)
+    compare(g, tr(*rays), rays, tr)
+
+
 def test_paths_over_the_pole(rt, ctx, orc, aniso_wl, aniso_grid):
     """A transmitter 3 deg from the north pole with rays heading north: the
     colatitude passes through zero (sin theta changes sign) on the way, far
