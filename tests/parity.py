@@ -11,10 +11,14 @@ agrees to 1e-6 with one of the three oracle results (same status).
 Mixed path: ground range and group path within 0.1 km and azimuth deviation
 within 0.001 deg, same status.  FP32 evaluation perturbs every right-hand
 side at the 1e-7 level, so a ray that misses is re-traced by the oracle with
-its elevation moved by +-1e-6 deg and its frequency scaled by 1 +- 5e-8 (X
-by about 1e-7).  If any of those moves an output by more than the tolerance
-or flips its status, the ray is ill-conditioned at FP32 level and counted
-apart; a ray that misses while conditioned is a failure.
+its launch direction tilted by +-1e-6 deg in the launch plane (the elevation)
+and across it, and with its frequency scaled by 1 +- 5e-8 (X by about 1e-7).
+If any of those moves an output by more than the tolerance or flips its
+status, the ray is ill-conditioned at FP32 level and counted apart; a ray
+that misses while conditioned is a failure.  (The tilt across the launch
+plane matters where the ground range is short: a near-vertical ray lands a
+few hundred metres from the transmitter, and the bearing of that point
+moves by more than 0.001 deg when it moves sideways by a few millimetres.)
 
 Every function takes whole arrays and re-traces only the rays that miss, in
 one oracle call, so that a full 112,400-ray sweep is classified in seconds.
@@ -128,6 +132,17 @@ def _mixed_ok(g, o, tol_km=TOL_KM, tol_deg=TOL_DEG):
     return num | (same & close)
 
 
+def tilt_across(elev, az, delta_deg):
+    """Launch direction (elevation, azimuth in deg) tilted by delta_deg
+    across the launch plane (toward azimuth + 90 deg); for a vertical launch
+    this tilts it toward azimuth + 90 deg."""
+    b, a, d = np.radians(elev), np.radians(az), np.radians(delta_deg)
+    up = np.sin(b)
+    north = np.cos(b) * np.cos(a) - d * np.sin(a)
+    east = np.cos(b) * np.sin(a) + d * np.cos(a)
+    return np.degrees(np.arctan2(up, np.hypot(north, east))), np.degrees(np.arctan2(east, north))
+
+
 def classify_mixed(gpu, ora, rays, trace_oracle, gpu_idx=None, tol_km=TOL_KM, tol_deg=TOL_DEG):
     """Mixed-precision tolerance on every ray.  Returns counts (n, n_within,
     n_ill, n_fail), the failures, and the max / RMS absolute errors of group
@@ -142,13 +157,17 @@ def classify_mixed(gpu, ora, rays, trace_oracle, gpu_idx=None, tol_km=TOL_KM, to
     miss = np.flatnonzero(~ok)
     ill = np.zeros(n, dtype=bool)
     if miss.size:
-        m4 = np.concatenate([miss] * 4)
-        pe = np.concatenate([elev[miss] - 1e-6, elev[miss] + 1e-6, elev[miss], elev[miss]])
-        pf = np.concatenate([freq[miss], freq[miss], freq[miss] * (1 - 5e-8), freq[miss] * (1 + 5e-8)])
-        pr = _take(trace_oracle(pe, az[m4], pf, mode[m4]), np.arange(4 * miss.size))
-        ref = _take(o, m4)
+        m6 = np.concatenate([miss] * 6)
+        e_m, a_m = elev[miss], az[miss]
+        (e_l, a_l), (e_r, a_r) = tilt_across(e_m, a_m, -1e-6), tilt_across(e_m, a_m, 1e-6)
+        pe = np.concatenate([e_m - 1e-6, e_m + 1e-6, e_m, e_m, e_l, e_r])
+        pa = np.concatenate([a_m, a_m, a_m, a_m, a_l, a_r])
+        pf = np.concatenate([freq[miss], freq[miss], freq[miss] * (1 - 5e-8), freq[miss] * (1 + 5e-8),
+                             freq[miss], freq[miss]])
+        pr = _take(trace_oracle(pe, pa, pf, mode[m6]), np.arange(6 * miss.size))
+        ref = _take(o, m6)
         moved = ~_mixed_ok(pr, ref, tol_km, tol_deg)
-        ill[miss] = moved.reshape(4, miss.size).any(axis=0)
+        ill[miss] = moved.reshape(6, miss.size).any(axis=0)
     fail = ~ok & ~ill
     same = (g["status"] == o["status"]) & (o["status"] != NUMERIC)
     stats = {}

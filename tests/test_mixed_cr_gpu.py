@@ -114,3 +114,26 @@ def test_mixed_tail_kernel_bit_identical_to_one_lane(rt, ctx):
     grid.close()
     for k in ("group_km", "range_km", "az_dev_deg", "status", "n_steps"):
         assert np.array_equal(one[k], tail[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("case", ["directions", "pole", "elevated"])
+def test_mixed_edge_cases(rt, ctx, orc, case):
+    """The FP64 edge cases in mixed precision: horizontal and vertical
+    launches, paths over the pole, a transmitter 100 m below the grid
+    bottom."""
+    wl = synth.aniso_fan_workload(0)
+    fan = {"directions": synth.Fan(30.0, 110.0, 0.0, np.array([0.0, 0.5, 89.5, 90.0]),
+                                   np.array([0.0, 90.0, 179.99, 180.0, -90.0, 359.99]),
+                                   np.array([6.0, 12.0]), (1, -1)),
+           "pole": synth.Fan(87.0, 110.0, 0.0, np.array([3.0, 8.0, 15.0, 25.0]), np.array([0.0, 1.0, 30.0]),
+                             np.array([5.0, 9.0]), (1, -1)),
+           "elevated": synth.Fan(30.0, 110.0, 59.9, np.array([0.0, 2.0, 10.0, 45.0]),
+                                 np.array([0.0, 45.0, 135.0]), np.array([6.0, 12.0]), (1, -1))}[case]
+    grid = rt.Grid(ctx, wl.grid)
+    try:
+        g = host(gpu_trace(rt, ctx, grid, wl, fan, precision="mixed", device_results=True))
+    finally:
+        grid.close()
+    rays = fan.expand()
+    tr = oracle_tracer(orc, wl, fan)
+    check_mixed(g, tr(*rays), rays, tr, case, max_ill_frac=0.1)
