@@ -325,23 +325,29 @@ def test_elevated_transmitter(rt, ctx, orc, aniso_wl, aniso_grid, tx_h_km):
     compare(g, tr(*rays), rays, tr)
 
 
+@pytest.mark.parametrize("interp", ["gd", "cr"])
 @pytest.mark.parametrize("B0", [0.0, synth.B0_DIPOLE_T])
-def test_smallest_grid(rt, ctx, orc, aniso_wl, B0):
+def test_smallest_grid(rt, ctx, orc, aniso_wl, B0, interp):
     """A grid of 4 x 5 x 6 nodes, the fewest an axis may have plus one and
     two: every axis has one or two cells, so the weights are evaluated on the
-    edge cells' extended range s in [-1, 2] almost everywhere."""
+    edge cells' extended range s in [-1, 2] almost everywhere (GD and the
+    Catmull-Rom comparator)."""
     geom = synth.GridGeom(4, 5, 6, 28.5, 1.0, 108.0, 1.0, 60.0, 90.0)
     small = synth.ionosphere_grid(geom, 3, B0_T=B0)
     wl = dataclasses.replace(aniso_wl, grid=small)
     fan = synth.Fan(30.0, 110.0, 0.0, np.array([5.0, 20.0, 40.0, 70.0]), np.array([0.0, 90.0, 200.0]),
                     np.array([4.0, 8.0]), (1, -1))
-    grid = rt.Grid(ctx, small)
+    grid = rt.Grid(ctx, small, interp=interp)
     try:
         g = gpu_trace(rt, ctx, grid, wl, fan)
     finally:
         grid.close()
     rays = fan.expand()
-    tr = oracle_tracer(orc, wl, fan)
+    med = orc.OracleMedium.from_grid(small, interp=interp)
+
+    def tr(e, a, f, m):
+        return orc.trace(med, e, a, f, m, B0=B0, R=geom.earth_radius_km, tx=(fan.tx_lat_deg, fan.tx_lon_deg, 0.0),
+                         step=wl.step_km, max_group=wl.max_group_km, exit_h=wl.exit_km)
     compare(g, tr(*rays), rays, tr)
 
 
