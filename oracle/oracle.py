@@ -107,11 +107,15 @@ def _bind(L):
 
 
 def lib():
+    """The oracle's shared object.  RTGD_ORACLE_LIB names another build of
+    the same interface instead (the pin tests' mutation check loads copies
+    of the oracle with planted mistakes this way)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("RTGD_ORACLE_LIB") or LIB
+        if path == LIB and not os.path.exists(LIB):
             build()
-        _lib = _bind(ctypes.CDLL(LIB))
+        _lib = _bind(ctypes.CDLL(path))
     return _lib
 
 
@@ -163,6 +167,9 @@ class OracleMedium:
         if grid is not None:
             g = grid.geom
             self._ne = np.ascontiguousarray(grid.values, dtype=np.float64)
+            if self._ne.shape != (g.n_lat, g.n_lon, g.n_h):
+                raise ValueError(f"grid values of shape {self._ne.shape}, geometry "
+                                 f"({g.n_lat}, {g.n_lon}, {g.n_h})")
             self.m.n_lat, self.m.n_lon, self.m.n_h = g.n_lat, g.n_lon, g.n_h
             self.m.lat0_deg, self.m.dlat_deg = g.lat0_deg, g.dlat_deg
             self.m.lon0_deg, self.m.dlon_deg = g.lon0_deg, g.dlon_deg

@@ -193,6 +193,14 @@ def test_outside_box_is_clamped_and_vacuum_below(orc):
     # above the top: constant continuation, d/dr = 0
     top = _eval_geo(orc, med, 29.1, 109.1, 130.0)
     assert top[1] == 0.0
+    # north and south of the box: the value of the north / south face,
+    # d/dtheta = 0, while the other partials are those of the face
+    for lat_out, lat_face in ((35.0, 30.5), (20.0, 28.0)):
+        out = _eval_geo(orc, med, lat_out, 109.3, 110.0)
+        face = _eval_geo(orc, med, lat_face, 109.3, 110.0)
+        assert out[2] == 0.0 and face[2] != 0.0
+        assert abs(out[0] - face[0]) <= 1e-12 * abs(face[0])
+        assert abs(out[3] - face[3]) <= 1e-12 * abs(face[3])
 
 
 def test_convergence_orders_value3_gradient2(orc):

@@ -310,3 +310,38 @@ def test_near_critical_band_status(orc):
     med = orc.OracleMedium.chapman(8.0, 300.0, 50.0, floor_km=60.0)
     r = orc.trace(med, [50.0, 51.0, 52.0, 53.0], 0.0, 10.0, exit_h=500.0)
     assert list(r["status"]) == [orc.GROUND, orc.GROUND, orc.ESCAPE, orc.ESCAPE]
+
+
+def _bearing_deg(lat1, lon1, lat2, lon2):
+    """Initial great-circle bearing, clockwise from north (spherical
+    trigonometry: the four-part formula)."""
+    p1, p2, dl = np.radians(lat1), np.radians(lat2), np.radians(lon2 - lon1)
+    return np.degrees(np.arctan2(np.sin(dl) * np.cos(p2),
+                                 np.cos(p1) * np.sin(p2) - np.sin(p1) * np.cos(p2) * np.cos(dl)))
+
+
+@pytest.mark.parametrize("east_gain", [0.2, -0.2])
+def test_azimuth_deviation_in_a_tilted_layer(orc, east_gain):
+    """A Chapman layer whose density grows eastward (or westward) by 20 %
+    across the box, no field: a ray launched north is refracted toward the
+    lower density, i.e. toward the higher refractive index, so it lands west
+    (east) of its launch plane and its azimuth deviation is negative
+    (positive), the two mirror images of each other.  The deviation is the
+    initial great-circle bearing to the landing point minus the launch
+    azimuth."""
+    from paper_2506_18579_amd.synth import Grid, GridGeom, chapman
+    geom = GridGeom(41, 41, 100, 20.0, 0.5, 100.0, 0.5, 60.0, 5.0)
+    prof = chapman(geom.heights(), 8.0, 300.0, 50.0)
+    lon = geom.lon0_deg + geom.dlon_deg * np.arange(geom.n_lon)
+    tilt = 1.0 + east_gain * (lon - 110.0) / 10.0
+    grid = Grid(geom, np.broadcast_to(prof[None, None, :] * tilt[None, :, None],
+                                      (geom.n_lat, geom.n_lon, geom.n_h)).copy())
+    med = orc.OracleMedium.from_grid(grid)
+    elev = np.array([15.0, 25.0, 35.0])
+    r = orc.trace(med, elev, np.zeros(3), 7.0, tx=(25.0, 110.0, 0.0), step=1.0, max_group=4000.0,
+                  exit_h=500.0)
+    assert np.all(r["status"] == 0)
+    dev = r["az_dev_deg"]
+    assert np.all(np.sign(dev) == -np.sign(east_gain)) and np.all(np.abs(dev) > 1e-3)
+    bearing = _bearing_deg(25.0, 110.0, r["land_lat_deg"], r["land_lon_deg"])
+    assert np.abs(dev - bearing).max() < 1e-9
