@@ -526,6 +526,15 @@ __device__ __forceinline__ void gather_rows(unsigned long long live, int &ray, L
 // always find room.  The state goes to the ray's
 // record, a ticket is taken, and the ray index is published under the
 // ticket (release).  The lane then idles and refills from the launch queue.
+// A member of the parameter block read from its device copy where it is
+// used (a volatile load the compiler cannot hoist), so that members a loop
+// needs only now and then hold no scalar registers across it.  The
+// promotion waves read their queue and counter addresses this way: kept in
+// scalar registers they spilled into vector lanes, a `v_readlane` each time
+// the stepping loop touched them.
+template <typename X>
+__device__ __forceinline__ X fresh(const X &v) { return *reinterpret_cast<const volatile X *>(&v); }
+
 template <typename T>
 __device__ __forceinline__ int promote_room(const TraceParams<T> &P, unsigned long long cm, int cap, int lane)
 {
@@ -777,32 +786,32 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
         // for it.
         const unsigned long long busy = __ballot(ray >= 0);
         const bool poll = busy == 0ull || (iter & 31) == 0;
-        if (!closing && P.handoff_threshold > 0 && poll) {
+        if (!closing && poll && fresh(Pp->handoff_threshold) > 0) {
             int live = 0, head = 0;
             if (lane == 0) {
-                live = __hip_atomic_load(P.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                head = __hip_atomic_load(P.queue_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                live = __hip_atomic_load(fresh(Pp->live), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                head = __hip_atomic_load(fresh(Pp->queue_head), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             live = __shfl(live, 0);
             head = __shfl(head, 0);
-            closing = head >= P.n_rays && live <= P.handoff_threshold;
+            closing = head >= fresh(Pp->n_rays) && live <= fresh(Pp->handoff_threshold);
         }
         // idle rows claim promoted rays
         if (poll && __ballot(ray < 0) != 0ull) {
             int r = -1;
-            if (lead && ray < 0) r = claim_promoted(P);
+            if (lead && ray < 0) r = claim_promoted(*Pp);
             r = __shfl(r, lead_lane);
             if (r >= 0) {
                 ray = r;
-                L = P.rec[ray].L;
+                L = fresh(Pp->rec)[ray].L;
                 sc.clear();
             }
         }
         if (closing) {
-            const int n = handoff_rows(lead && ray >= 0, ray, L, P.n_handoff, P.handoff, lane);
+            const int n = handoff_rows(lead && ray >= 0, ray, L, fresh(Pp->n_handoff), fresh(Pp->handoff), lane);
             if (lane == 0 && n > 0) {
-                atomicSub(P.live, n);
-                atomicSub(P.promo_live, n);
+                atomicSub(fresh(Pp->live), n);
+                atomicSub(fresh(Pp->promo_live), n);
             }
             ray = -1;
         }
@@ -818,8 +827,8 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             }
             const int n = __popcll(__ballot(lead && st >= 0));
             if (lane == 0 && n > 0) {
-                if (P.handoff_threshold > 0) atomicSub(P.live, n);
-                atomicSub(P.promo_live, n);
+                if (fresh(Pp->handoff_threshold) > 0) atomicSub(fresh(Pp->live), n);
+                atomicSub(fresh(Pp->promo_live), n);
             }
             idling = false;
         } else {
@@ -829,9 +838,9 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             // after it is final and no ticket can be left unclaimed.
             int alive = 0, popped = 0, pushed = 0;
             if (lane == 0) {
-                alive = __hip_atomic_load(P.producers_alive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                pushed = __hip_atomic_load(P.promo_push, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                popped = __hip_atomic_load(P.promo_pop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                alive = __hip_atomic_load(fresh(Pp->producers_alive), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                pushed = __hip_atomic_load(fresh(Pp->promo_push), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                popped = __hip_atomic_load(fresh(Pp->promo_pop), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             alive = __shfl(alive, 0);
             popped = __shfl(popped, 0);
@@ -841,8 +850,8 @@ __device__ __forceinline__ void promote_body(const TraceParams<T> &P, const Trac
             if (!idling) {
                 idling = true;
                 idle_t0 = now;
-            } else if (now - idle_t0 > P.idle_ticks) {
-                if (lane == 0) atomicAdd(P.promo_err, 1);
+            } else if (now - idle_t0 > fresh(Pp->idle_ticks)) {
+                if (lane == 0) atomicAdd(fresh(Pp->promo_err), 1);
                 break;
             }
             __builtin_amdgcn_s_sleep(32);
