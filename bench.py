@@ -66,7 +66,7 @@ def measured_traffic(precision):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample-stride", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")

@@ -128,7 +128,7 @@ typedef struct {
                                file, 2 = two waves per SIMD; 0 = default  */
     int32_t ray_order;      /* scheduling knob, results unchanged: order in
                                which waves take rays from the queue; 0 =
-                               default (index order), 1 = index order,
+                               default (3), 1 = index order,
                                2 = strided: q -> q * s mod n_rays with s
                                coprime to n_rays near 0.618 n_rays, which
                                spreads neighbouring (similar) rays over
@@ -145,7 +145,7 @@ typedef struct {
                                (n_r falling to a positive local minimum below
                                0.02 |n|: such rays are often trapped later)
                                and rays older than promote_age steps;
-                               0 = default (16 for launches of at least
+                               0 = default (32 for launches of at least
                                8192 rays, else none), -1 = none, at most 64;
                                ignored with tail_threshold = -2.  With
                                promotion on, an rt_trace launch holds at
@@ -387,10 +387,11 @@ void rt_plan_destroy(rt_plan *plan);
  * combine with it), promote_waves in
  * {16, 32, 64} with promote_age -1, each with cu_layout 2 and 1; the first
  * stage runs without promotion; one untimed run, then the median device
- * time of three), times the fastest and the library defaults again, seven
- * single launches each, interleaved, keeps the fastest if its median beats
- * the defaults' by at least 2 % (else the defaults, all six fields 0;
- * best_ms and default_ms are those medians) and writes base with
+ * time of three), times the three fastest and the library defaults again,
+ * nine single launches each, interleaved, keeps the one with the lowest
+ * median if that beats the defaults' by at least 2 % (else the defaults,
+ * all six fields 0; best_ms and default_ms are those medians) and writes
+ * base with
  * those six fields replaced to *tuned.  Choices are cached in the process under a key made of the
  * device's CU count, the grid shape and interpolation, precision, field on
  * or off and the ray count rounded to a power of two; a cached key is

@@ -433,10 +433,10 @@ static_assert(sizeof(TraceParams<float>) <= sizeof(TraceParams<double>),
               "the workspace reserves room for the FP64 parameter block");
 
 // Promotion waves (rt_trace_opts::promote_waves): at most, and the library
-// defaults: 16 waves for launches of at least 8192 rays (smaller ones keep
+// defaults: 32 waves for launches of at least 8192 rays (smaller ones keep
 // every wave for one-lane work), promoting trapped and grazing rays only.
 constexpr int kMaxPromoteWaves = 64;
-constexpr int kDefaultPromoteWaves = 16;
+constexpr int kDefaultPromoteWaves = 32;
 constexpr int kDefaultPromoteMinRays = 8192;
 constexpr int kDefaultPromoteAge = 0;
 
@@ -564,7 +564,7 @@ void finish_job(rt_ctx *ctx, TraceJob &job, const rt_trace_opts &opts)
     job.inwave = tail == -2 ? 1 : 0;
     job.tail = tail > 0 ? int(std::min<int64_t>(tail, n64)) : 0;
     job.perm = opts.ray_order == 2 ? visit_stride(n64) : 1;
-    job.binned = opts.ray_order == 3;
+    job.binned = opts.ray_order == 3 || opts.ray_order == 0;   // the default: sorted by wave mode
     // promotion runs beside the one-lane waves; not with the in-wave switch
     const int pw = opts.promote_waves != 0 ? opts.promote_waves
                  : (n64 >= kDefaultPromoteMinRays ? kDefaultPromoteWaves : 0);
@@ -1638,6 +1638,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
     };
     double best = 1e300;
     TuneVal bv{0, 0, 0, 0, 0, 0};
+    std::vector<std::pair<double, TuneVal>> tried;   // every candidate and its first-round median
     rt_trace_opts o = *base;
     o.tail_threshold = 0;
     o.waves_per_simd = 0;
@@ -1659,6 +1660,7 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
                 double ms = 0;
                 st = time_opts(o, ms);
                 ++inf.n_candidates;
+                if (st == RT_OK) tried.push_back({ms, TuneVal{tl, oc, od, -1, 0, 0}});
                 if (st == RT_OK && ms < best) { best = ms; bv = TuneVal{tl, oc, od, -1, 0, 0}; }
                 if (st == RT_OK && tl != -2 && ms < best_h) { best_h = ms; bh = TuneVal{tl, oc, od, -1, 0, 0}; }
             }
@@ -1682,42 +1684,57 @@ extern "C" rt_status rt_autotune(rt_ctx *ctx, const rt_grid *grid, const rt_fan 
                 double ms = 0;
                 st = time_opts(o, ms);
                 ++inf.n_candidates;
+                const TuneVal v{base_v.tail_threshold, base_v.waves_per_simd, base_v.ray_order, pr[0], pr[1], lay};
+                if (st == RT_OK) tried.push_back({ms, v});
                 if (st == RT_OK && ms < best) {
                     best = ms;
-                    bv = TuneVal{base_v.tail_threshold, base_v.waves_per_simd, base_v.ray_order, pr[0], pr[1],
-                                 lay};
+                    bv = v;
                 }
             }
         }
     }
     // Confirmation: single launches vary by several per cent from run to run
-    // (the last rays' 16-lane steps set the launch time), so the winner and
-    // the defaults are timed again, interleaved, and the winner is kept only
-    // if its median is clearly below the defaults'.
-    if (st == RT_OK && !(bv.tail_threshold == 0 && bv.waves_per_simd == 0 && bv.ray_order == 0 &&
-                         bv.promote_waves == 0 && bv.promote_age == 0 && bv.cu_layout == 0)) {
-        rt_trace_opts ob = *base, od = *base;
-        ob.tail_threshold = bv.tail_threshold;
-        ob.waves_per_simd = bv.waves_per_simd;
-        ob.ray_order = bv.ray_order;
-        ob.promote_waves = bv.promote_waves;
-        ob.promote_age = bv.promote_age;
-        ob.cu_layout = bv.cu_layout;
+    // (the last rays' 16-lane steps set the launch time, and candidates are
+    // often within that of each other), so the three fastest candidates and
+    // the defaults are timed again, nine launches each, interleaved; the
+    // candidate with the lowest median is kept only if that median is
+    // clearly below the defaults'.
+    if (st == RT_OK && !tried.empty()) {
+        std::stable_sort(tried.begin(), tried.end(),
+                         [](const std::pair<double, TuneVal> &a, const std::pair<double, TuneVal> &b) {
+                             return a.first < b.first;
+                         });
+        const size_t nf = std::min<size_t>(3, tried.size());
+        constexpr int kReps = 9;
+        std::vector<rt_trace_opts> os(nf + 1, *base);
+        for (size_t c = 0; c < nf; ++c) {
+            const TuneVal &v = tried[c].second;
+            os[c].tail_threshold = v.tail_threshold;
+            os[c].waves_per_simd = v.waves_per_simd;
+            os[c].ray_order = v.ray_order;
+            os[c].promote_waves = v.promote_waves;
+            os[c].promote_age = v.promote_age;
+            os[c].cu_layout = v.cu_layout;
+        }
+        rt_trace_opts &od = os[nf];      // the library defaults
         od.tail_threshold = od.waves_per_simd = od.ray_order = 0;
         od.promote_waves = od.promote_age = od.cu_layout = 0;
-        ob.results_mem = od.results_mem = RT_MEM_DEVICE;
-        double tb[7], td[7];
-        for (int rep = 0; rep < 7 && st == RT_OK; ++rep) {
-            st = rt_trace(ctx, grid, fan, &ob, &r);
-            tb[rep] = r.kernel_ms;
-            if (st == RT_OK) st = rt_trace(ctx, grid, fan, &od, &r);
-            td[rep] = r.kernel_ms;
-        }
+        for (auto &oo : os) oo.results_mem = RT_MEM_DEVICE;
+        std::vector<std::vector<double>> t(nf + 1);
+        for (int rep = 0; rep < kReps && st == RT_OK; ++rep)
+            for (size_t c = 0; c <= nf && st == RT_OK; ++c) {
+                st = rt_trace(ctx, grid, fan, &os[c], &r);
+                t[c].push_back(r.kernel_ms);
+            }
         if (st == RT_OK) {
-            std::sort(tb, tb + 7);
-            std::sort(td, td + 7);
-            best = tb[3];
-            inf.default_ms = td[3];
+            for (auto &tc : t) std::sort(tc.begin(), tc.end());
+            inf.default_ms = t[nf][kReps / 2];
+            best = 1e300;
+            for (size_t c = 0; c < nf; ++c)
+                if (t[c][kReps / 2] < best) {
+                    best = t[c][kReps / 2];
+                    bv = tried[c].second;
+                }
         }
     }
     (void)hipFree(buf);
