@@ -253,7 +253,9 @@ __device__ __forceinline__ float pick(unsigned m, float a, float b)
     return __uint_as_float(bfi(m, __float_as_uint(b), __float_as_uint(a)));
 }
 constexpr int kRowRor8 = 0x128;          // lane i <- lane (i + 8) mod 16 within 16
-constexpr int kRowRor4 = 0x124;          // lane i <- lane (i + 4) mod 16 within 16
+constexpr int kRowShr4 = 0x114;          // lane i <- lane i - 4 within 16 (0 for i < 4)
+constexpr int kQuadEven = 0xA0;          // quad_perm(0, 0, 2, 2): odd lanes read lane - 1
+constexpr int kQuadOdd = 0xF5;           // quad_perm(1, 1, 3, 3): even lanes read lane + 1
 
 // The grid lives in global memory; saying so (address space 1) lets the
 // compiler use global loads, which do not share a wait counter with the
@@ -271,8 +273,9 @@ __device__ __forceinline__ void col_load(gptr<T> p, T u[4])
 
 // Contraction order, shared by every kernel variant so that all give the
 // same rounded result: per column, heights in a fused chain (value and
-// d/dh); per latitude row, the four weighted columns as
-// (col0 + col1) + (col2 + col3); over rows, (row0 + row2) + (row1 + row3).
+// d/dh); per latitude row, the weighted columns in pairs,
+// fma(col1, w1, col0 w0) + fma(col3, w3, col2 w2); over rows, the same
+// pairing of rows (0, 1) and (2, 3).
 template <typename T>
 __device__ __forceinline__ void col_contract(const T u[4], const T wh[4], const T dwh[4], T &cv, T &dcv)
 {
@@ -379,33 +382,25 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
         T wo[4], dwo[4], wl[4], dwl[4];
         weights4<T, IP>(T(so_), wo, dwo);
         weights4<T, IP>(T(sl_), wl, dwl);
-        T pv[4], pla[4], plo[4], phh[4];
+        T s0[4], s1[4], s2[4];   // per lat offset a: sums over the lon offsets b
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            T t0[4], t1[4], t2[4];
+            T cv[4], dcv[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 T uu[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) uu[c] = sc.u[a][b][c] - uref;
-                T cv, dcv;
-                col_contract<T>(uu, wh, dwh, cv, dcv);
-                t0[b] = cv * wo[b];
-                t1[b] = cv * dwo[b];
-                t2[b] = dcv * wo[b];
+                col_contract<T>(uu, wh, dwh, cv[b], dcv[b]);
             }
-            const T s0 = (t0[0] + t0[1]) + (t0[2] + t0[3]);
-            const T s1 = (t1[0] + t1[1]) + (t1[2] + t1[3]);
-            const T s2 = (t2[0] + t2[1]) + (t2[2] + t2[3]);
-            pv[a] = s0 * wl[a];
-            pla[a] = s0 * dwl[a];
-            plo[a] = s1 * wl[a];
-            phh[a] = s2 * wl[a];
+            s0[a] = fm(cv[1], wo[1], cv[0] * wo[0]) + fm(cv[3], wo[3], cv[2] * wo[2]);
+            s1[a] = fm(cv[1], dwo[1], cv[0] * dwo[0]) + fm(cv[3], dwo[3], cv[2] * dwo[2]);
+            s2[a] = fm(dcv[1], wo[1], dcv[0] * wo[0]) + fm(dcv[3], wo[3], dcv[2] * wo[2]);
         }
-        v = (pv[0] + pv[2]) + (pv[1] + pv[3]);
-        glat = (pla[0] + pla[2]) + (pla[1] + pla[3]);
-        glon = (plo[0] + plo[2]) + (plo[1] + plo[3]);
-        gh = (phh[0] + phh[2]) + (phh[1] + phh[3]);
+        v = fm(s0[1], wl[1], s0[0] * wl[0]) + fm(s0[3], wl[3], s0[2] * wl[2]);
+        glat = fm(s0[1], dwl[1], s0[0] * dwl[0]) + fm(s0[3], dwl[3], s0[2] * dwl[2]);
+        glon = fm(s1[1], wl[1], s1[0] * wl[0]) + fm(s1[3], wl[3], s1[2] * wl[2]);
+        gh = fm(s2[1], wl[1], s2[0] * wl[0]) + fm(s2[3], wl[3], s2[2] * wl[2]);
     } else {
         T wo, dwo, wl, dwl, w1, dw1;
         eval_piece<T, IP>(sc.pb, T(so_), wo, dwo);
@@ -424,30 +419,32 @@ __device__ __forceinline__ void medium(const GridDev<T> &g, const T *vals, doubl
         for (int c = 0; c < 4; ++c) uu[c] = sc.u[0][0][c] - uref;
         T cv, dcv;
         col_contract<T>(uu, wh, dwh, cv, dcv);
+        // within the quad (lon offsets b): the odd lane of each pair adds
+        // its weighted column to the even lane's product by one FMA, then
+        // lanes 1 and 3 add the two pairs (equal on both)
         T t0 = cv * wo, t1 = cv * dwo, t2 = dcv * wo;
-        // within the quad (lon offsets b): lanes b, b^1 form t_b + t_b^1,
-        // then (t0 + t1) + (t2 + t3) -- equal on all four lanes
-        t0 = t0 + dpp<kQuadXor1>(t0);
-        t1 = t1 + dpp<kQuadXor1>(t1);
-        t2 = t2 + dpp<kQuadXor1>(t2);
+        t0 = fm(cv, wo, dpp<kQuadEven>(t0));
+        t1 = fm(cv, dwo, dpp<kQuadEven>(t1));
+        t2 = fm(dcv, wo, dpp<kQuadEven>(t2));
         const T s0 = t0 + dpp<kQuadXor2>(t0);
         const T s1 = t1 + dpp<kQuadXor2>(t1);
         const T s2 = t2 + dpp<kQuadXor2>(t2);
-        // The four lanes of a quad now hold the same sums; lane b of each
-        // quad takes one of the four row products, q = b: the value s0 wl,
-        // d/dlat s0 dwl, d/dlon s1 wl, d/dh s2 wl, and sums it over the lat
-        // offsets a across the row: rotating by 8 lanes pairs a with a + 2,
-        // then by 4 pairs (a, a + 2) with (a + 1, a + 3).  Lane q of the row
-        // then holds quantity q, which the row broadcasts.
-        const T lhs = pick(sc.m3, pick(sc.m2, s0, s1), s2);
+        // Only the odd lanes of a quad hold the sums.  Lane b of each quad
+        // takes one of the four row products, q = b: the value s0 wl, d/dlat
+        // s0 dwl, d/dlon s1 wl, d/dh s2 wl; lanes 0 and 2 receive their sum
+        // (s0, s1) from lanes 1 and 3.
+        const T lhs = pick(sc.m3, dpp<kQuadOdd>(pick(sc.m3, s0, s1)), s2);
         const T rhs = pick(sc.m1, wl, dwl);
+        // over the lat offsets a (quads of the row), paired the same way:
+        // quads 1 and 3 hold the pairs, then each adds the other's
         T p = lhs * rhs;
+        p = fm(lhs, rhs, dpp<kRowShr4>(p));
         p = p + dpp<kRowRor8>(p);
-        p = p + dpp<kRowRor4>(p);
-        v = row_bcast<0>(p);
-        glat = row_bcast<1>(p);
-        glon = row_bcast<2>(p);
-        gh = row_bcast<3>(p);
+        // lane 4 + q of the row holds quantity q, which the row broadcasts
+        v = row_bcast<4>(p);
+        glat = row_bcast<5>(p);
+        glon = row_bcast<6>(p);
+        gh = row_bcast<7>(p);
     }
     // index space -> physical: dt_h/dr = 1/dh, dt_lat/dth = lat_a,
     // dt_lon/dph = lon_a
