@@ -41,9 +41,9 @@ PEAK_FP32_VALU_TFLOPS = 157.3     # packed FP32; 78.6 without packed math
 # + WRITE_SIZE x 1.000 KiB (factors from a 1 GiB device copy in the same
 # runs).  Valid only for the device sources (per-step arithmetic and trace
 # kernels) with these hashes; otherwise reported as null.
-TRAFFIC_BYTES = {"fp64": (76666 + 48774) * 1024, "mixed": (70742 + 48975) * 1024}
+TRAFFIC_BYTES = {"fp64": (76266 + 48825) * 1024, "mixed": (70832 + 48827) * 1024}
 TRAFFIC_SOURCES = {
-    "rtgd_device.h": "3e2c4319b8619d3da6b8ddb0daeceffc590edc638060ee7b9604b9becf17691e",
+    "rtgd_device.h": "6cfa466b2e916828fb213d16883c5265098ee0ee1f6d0ce305cdbbc2deb21403",
     "rtgd_kernels.h": "47926ca35cc4a5ee319714342d675ef9413186b7738638239101c8a88df59c6d",
 }
 

@@ -297,16 +297,15 @@ struct StencilCache {
     T u[NA][NA][4];
     T uref;                   // node (1, 1, 1), the mixed path's reference
     Piece<T> pa, pb;          // LANES = 16: weights of this lane's a and b
-    unsigned m1, m2, m3;      // LANES = 16: all ones where lane & 3 is 1, 2, 3
+    unsigned m1, m3;          // LANES = 16: all ones where lane & 3 is 1, 3
     __device__ void clear() { il = -1; jl = -1; kh = -1; }
     __device__ void set_masks(int lane)
     {
         m1 = (lane & 3) == 1 ? ~0u : 0u;
-        m2 = (lane & 3) == 2 ? ~0u : 0u;
         m3 = (lane & 3) == 3 ? ~0u : 0u;
         // opaque to the compiler from here on: it would turn pick() back
         // into selects on SGPR lane masks, which crowd the SGPRs
-        asm volatile("" : "+v"(m1), "+v"(m2), "+v"(m3));
+        asm volatile("" : "+v"(m1), "+v"(m3));
     }
 };
 
