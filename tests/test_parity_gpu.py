@@ -454,7 +454,7 @@ def test_tail_kernel_is_bit_identical(rt, ctx, aniso_wl, aniso_grid, precision):
 def test_promotion_is_bit_identical(rt, ctx, precision):
     """Promotion waves take trapped, grazing and old rays over while the
     one-lane waves run; outputs are identical with promotion off, at the
-    default (16 waves for this fan, trapped and grazing rays, one four-wave
+    default (32 waves for this fan, trapped and grazing rays, one four-wave
     work-group per CU), with one-wave work-groups, with the most waves, with
     a small age (many rays promoted, the queue kept full), and with the tail
     kernel off (promoted rays run to the end)."""
