@@ -302,8 +302,12 @@ rt_status rt_ionogram(rt_ctx *ctx, const rt_fan *fan, const rt_results *res, dou
  * options and whose outputs fit in the arena are launched together as one
  * batch on that slot (one persistent kernel over all their rays, each
  * request through its own grid snapshot); launches in different slots run
- * concurrently on the device.  rt_server_poll launches queued requests as
- * slots and memory free up and reports finished ones.  A finished
+ * concurrently on the device.  A batch of at least 65536 rays waits while
+ * another slot's launch of that size is still in its one-lane phase (it
+ * starts when that launch reaches its tail kernel), so that two large
+ * launches do not run their bulks side by side.  rt_server_poll launches
+ * queued requests as slots and memory free up and reports finished ones
+ * (the server makes progress only when submit or poll is called).  A finished
  * request keeps its outputs in the arena until rt_server_fetch copies them
  * out and releases the memory.  Per-ray arithmetic does not depend on the
  * slot or on what else runs, so a request's results are bit-identical alone

@@ -1076,6 +1076,8 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evm = nullptr;      // recorded after the trace kernel (before the tail kernel)
+    bool big = false;              // the running launch has at least kStaggerRays rays
     char *dev = nullptr;
     size_t dev_bytes = 0;
     char *host = nullptr;          // pinned
@@ -1138,27 +1140,53 @@ struct rt_server {
     int64_t next_id = 1;
     int max_batch_requests = 256;
     int64_t max_batch_rays = 1 << 20;
+    std::vector<void *> retired_dev, retired_host;   // replaced slot buffers, freed when every slot is idle
 };
 
 namespace {
 
-rt_status slot_reserve(rt_ctx *ctx, Slot &sl, size_t dev_bytes, size_t host_bytes)
+// Batches of at least this many rays start staggered (see schedule).
+constexpr int64_t kStaggerRays = 1 << 16;
+
+// A slot's buffers grow while launches of the other slots may be running.
+// hipFree and hipHostFree synchronize the device, so freeing the replaced
+// buffers here would hold the scheduler (and every idle slot) until those
+// launches end: they are retired instead, and freed once every slot is
+// idle (or with the server).  A buffer grows to a quarter more than asked,
+// so that growth is rare.
+rt_status slot_reserve(rt_server *srv, Slot &sl, size_t dev_bytes, size_t host_bytes)
 {
+    rt_ctx *ctx = srv->ctx;
     if (dev_bytes > sl.dev_bytes) {
-        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.dev) srv->retired_dev.push_back(sl.dev);
         sl.dev = nullptr;
         sl.dev_bytes = 0;
-        HIP_OR_FAIL(ctx, hipMalloc(&sl.dev, dev_bytes));
-        sl.dev_bytes = dev_bytes;
+        const size_t want = dev_bytes + dev_bytes / 4;
+        HIP_OR_FAIL(ctx, hipMalloc(&sl.dev, want));
+        sl.dev_bytes = want;
     }
     if (host_bytes > sl.host_bytes) {
-        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.host) srv->retired_host.push_back(sl.host);
         sl.host = nullptr;
         sl.host_bytes = 0;
-        HIP_OR_FAIL(ctx, hipHostMalloc(&sl.host, std::max<size_t>(host_bytes, 1 << 16), hipHostMallocDefault));
-        sl.host_bytes = std::max<size_t>(host_bytes, 1 << 16);
+        const size_t want = std::max<size_t>(host_bytes + host_bytes / 4, 1 << 16);
+        HIP_OR_FAIL(ctx, hipHostMalloc(&sl.host, want, hipHostMallocDefault));
+        sl.host_bytes = want;
     }
     return RT_OK;
+}
+
+// Free the retired slot buffers if no slot has a launch in flight.
+void free_retired(rt_server *srv, bool force)
+{
+    if (srv->retired_dev.empty() && srv->retired_host.empty()) return;
+    if (!force)
+        for (const Slot &sl : srv->slots)
+            if (!sl.reqs.empty()) return;
+    for (void *p : srv->retired_dev) (void)hipFree(p);
+    for (void *p : srv->retired_host) (void)hipHostFree(p);
+    srv->retired_dev.clear();
+    srv->retired_host.clear();
 }
 
 // Continuous batching: while a slot is idle, take the head of the FIFO queue
@@ -1170,6 +1198,7 @@ rt_status slot_reserve(rt_ctx *ctx, Slot &sl, size_t dev_bytes, size_t host_byte
 // waits until the arena can hold its outputs.
 rt_status schedule(rt_server *srv)
 {
+    free_retired(srv, false);
     while (!srv->queue.empty()) {
         Slot *slot = nullptr;
         for (Slot &sl : srv->slots)
@@ -1190,6 +1219,22 @@ rt_status schedule(rt_server *srv)
             rays += r.seg.n_rays;
         }
         if (ids.empty()) return RT_OK;                        // wait for memory
+        // Staggered start: a large batch waits while another slot's large
+        // launch is still in its one-lane phase.  Its persistent grid holds
+        // every SIMD then, so the two would run their bulks side by side and
+        // the first one's tail kernel would find no SIMD until the second's
+        // one-lane waves drain; started at the first one's tail, the second
+        // runs its bulk beside that launch's last rays.
+        if (rays >= kStaggerRays) {
+            bool wait = false;
+            for (const Slot &sl : srv->slots)
+                if (&sl != slot && !sl.reqs.empty() && sl.big && hipEventQuery(sl.evm) == hipErrorNotReady)
+                    wait = true;
+            if (wait) {
+                for (int64_t id : ids) srv->arena.release(srv->reqs[id].off, srv->reqs[id].bytes);
+                return RT_OK;
+            }
+        }
         for (int64_t id : ids)
             srv->queue.erase(std::find(srv->queue.begin(), srv->queue.end(), id));
         TraceJob job;
@@ -1205,8 +1250,11 @@ rt_status schedule(rt_server *srv)
         }
         finish_job(srv->ctx, job, srv->reqs[ids[0]].opts);
         const Layout lay = job_layout(job);
-        rt_status st = slot_reserve(srv->ctx, *slot, lay.dev_bytes, lay.host_bytes);
-        if (st == RT_OK) st = enqueue_job(srv->ctx, slot->stream, job, slot->dev, slot->host, slot->ev0, slot->ev1);
+        rt_status st = slot_reserve(srv, *slot, lay.dev_bytes, lay.host_bytes);
+        if (st == RT_OK)
+            st = enqueue_job(srv->ctx, slot->stream, job, slot->dev, slot->host, slot->ev0, slot->ev1, nullptr,
+                             slot->evm);
+        slot->big = rays >= kStaggerRays;
         if (st != RT_OK) {
             // leave the requests queued at the head, in order, without memory
             for (auto it = ids.rbegin(); it != ids.rend(); ++it) {
@@ -1255,7 +1303,8 @@ extern "C" rt_status rt_server_create(rt_ctx *ctx, const rt_server_opts *opts, r
     for (auto &sl : srv->slots) {
         // non-blocking streams at the default priority
         if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess) {
+            (e = hipEventCreate(&sl.ev0)) != hipSuccess || (e = hipEventCreate(&sl.ev1)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.evm, hipEventDisableTiming)) != hipSuccess) {
             rt_server_destroy(srv);
             return fail(ctx, RT_E_DEVICE, std::string("server stream setup: ") + hipGetErrorString(e));
         }
@@ -1273,9 +1322,11 @@ extern "C" void rt_server_destroy(rt_server *srv)
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.ev0) (void)hipEventDestroy(sl.ev0);
         if (sl.ev1) (void)hipEventDestroy(sl.ev1);
+        if (sl.evm) (void)hipEventDestroy(sl.evm);
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.host) (void)hipHostFree(sl.host);
     }
+    free_retired(srv, true);
     if (srv->arena.base) (void)hipFree(srv->arena.base);
     delete srv;
 }
