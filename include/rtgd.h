@@ -348,7 +348,9 @@ rt_status rt_server_submit(rt_server *srv, const rt_grid *grid, const rt_fan *fa
 rt_status rt_server_poll(rt_server *srv, rt_request_info *done, int32_t max, int32_t *n_done);
 /* Copy a finished request's per-ray outputs into res (arrays of n_rays,
  * host or device memory per mem; NULL pointers skipped), release its arena
- * memory and forget it.  RT_E_INVALID for an unknown or unfinished id. */
+ * memory and forget it.  To host memory the outputs go through the
+ * server's pinned staging (one device copy).  Blocks until the copy is
+ * done.  RT_E_INVALID for an unknown or unfinished id. */
 rt_status rt_server_fetch(rt_server *srv, int64_t id, rt_results *res, int32_t mem);
 /* Drop a queued request (RT_OK) or mark a running one to be discarded when
  * it finishes (RT_OK); RT_E_INVALID for an unknown id. */

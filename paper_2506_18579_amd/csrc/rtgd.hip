@@ -1141,6 +1141,8 @@ struct rt_server {
     int max_batch_requests = 256;
     int64_t max_batch_rays = 1 << 20;
     std::vector<void *> retired_dev, retired_host;   // replaced slot buffers, freed when every slot is idle
+    char *fetch = nullptr;     // pinned staging for rt_server_fetch to host memory
+    size_t fetch_bytes = 0;
 };
 
 namespace {
@@ -1327,6 +1329,7 @@ extern "C" void rt_server_destroy(rt_server *srv)
         if (sl.host) (void)hipHostFree(sl.host);
     }
     free_retired(srv, true);
+    if (srv->fetch) (void)hipHostFree(srv->fetch);
     if (srv->arena.base) (void)hipFree(srv->arena.base);
     delete srv;
 }
@@ -1425,16 +1428,41 @@ extern "C" rt_status rt_server_fetch(rt_server *srv, int64_t id, rt_results *res
     Request &r = it->second;
     const size_t N = size_t(r.seg.n_rays);
     if (N > 0) {
-        hipMemcpyKind kind = mem == RT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
         double *dst[7] = {res->group_km, res->phase_km, res->range_km, res->az_dev_deg,
                           res->apogee_km, res->land_lat_deg, res->land_lon_deg};
-        for (int k = 0; k < 7; ++k)
-            if (dst[k]) HIP_OR_FAIL(ctx, hipMemcpyAsync(dst[k], r.seg.out[k], N * 8, kind, ctx->stream));
-        if (res->status)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, r.seg.status, N * 4, kind, ctx->stream));
-        if (res->n_steps)
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, r.seg.nsteps, N * 4, kind, ctx->stream));
-        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        if (mem == RT_MEM_HOST) {
+            // The request's outputs lie in one block of the arena (seven
+            // FP64 arrays, then status and step count): one copy to pinned
+            // staging, then host copies to the caller's arrays, rather than
+            // nine copies to (pageable) caller memory.
+            const size_t bytes = N * (7 * 8 + 2 * 4);
+            if (bytes > srv->fetch_bytes) {
+                if (srv->fetch) srv->retired_host.push_back(srv->fetch);   // freed when every slot is idle
+                srv->fetch = nullptr;
+                srv->fetch_bytes = 0;
+                const size_t want = std::max<size_t>(bytes + bytes / 4, 1 << 20);
+                HIP_OR_FAIL(ctx, hipHostMalloc(reinterpret_cast<void **>(&srv->fetch), want, hipHostMallocDefault));
+                srv->fetch_bytes = want;
+            }
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(srv->fetch, r.seg.out[0], bytes, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+            for (int k = 0; k < 7; ++k)
+                if (dst[k]) std::memcpy(dst[k], srv->fetch + size_t(k) * N * 8, N * 8);
+            if (res->status) std::memcpy(res->status, srv->fetch + 7 * N * 8, N * 4);
+            if (res->n_steps) std::memcpy(res->n_steps, srv->fetch + 7 * N * 8 + N * 4, N * 4);
+        } else {
+            for (int k = 0; k < 7; ++k)
+                if (dst[k])
+                    HIP_OR_FAIL(ctx, hipMemcpyAsync(dst[k], r.seg.out[k], N * 8, hipMemcpyDeviceToDevice,
+                                                    ctx->stream));
+            if (res->status)
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(res->status, r.seg.status, N * 4, hipMemcpyDeviceToDevice,
+                                                ctx->stream));
+            if (res->n_steps)
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(res->n_steps, r.seg.nsteps, N * 4, hipMemcpyDeviceToDevice,
+                                                ctx->stream));
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        }
         srv->arena.release(r.off, r.bytes);
     }
     res->total_steps = r.info.total_steps;
