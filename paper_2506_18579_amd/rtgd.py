@@ -478,17 +478,26 @@ class Server:
             if n.value < len(self._buf):
                 return out
 
-    def fetch(self, rid: int, n_rays: int) -> dict:
-        """Per-ray outputs of a finished request (numpy, host)."""
-        out = {k: np.empty(n_rays, dtype=np.float64) for k in OUT_DOUBLE}
-        out.update({k: np.empty(n_rays, dtype=np.int32) for k in OUT_INT})
+    def fetch(self, rid: int, n_rays: int, device: bool = False) -> dict:
+        """Per-ray outputs of a finished request: numpy arrays on the host,
+        or (device=True) torch tensors on the context's GPU."""
         r = Results()
+        if device:
+            import torch
+            dev = torch.device("cuda", self.ctx.device)
+            out = {k: torch.empty(n_rays, dtype=torch.float64, device=dev) for k in OUT_DOUBLE}
+            out.update({k: torch.empty(n_rays, dtype=torch.int32, device=dev) for k in OUT_INT})
+            ptr = lambda t, P: ctypes.cast(ctypes.c_void_p(t.data_ptr()), P)
+        else:
+            out = {k: np.empty(n_rays, dtype=np.float64) for k in OUT_DOUBLE}
+            out.update({k: np.empty(n_rays, dtype=np.int32) for k in OUT_INT})
+            ptr = lambda a, P: a.ctypes.data_as(P)
         for k in OUT_DOUBLE:
-            setattr(r, k, out[k].ctypes.data_as(_DP))
+            setattr(r, k, ptr(out[k], _DP))
         for k in OUT_INT:
-            setattr(r, k, out[k].ctypes.data_as(_IP))
-        self.ctx.check(lib().rt_server_fetch(self.h, int(rid), ctypes.byref(r), RT_MEM_HOST),
-                       "rt_server_fetch")
+            setattr(r, k, ptr(out[k], _IP))
+        self.ctx.check(lib().rt_server_fetch(self.h, int(rid), ctypes.byref(r),
+                                             RT_MEM_DEVICE if device else RT_MEM_HOST), "rt_server_fetch")
         out["total_steps"] = int(r.total_steps)
         out["kernel_ms"] = float(r.kernel_ms)
         return out

@@ -116,6 +116,46 @@ def test_large_merged_launch_matches_alone(rt, ctx, grids, precision, cu_layout)
         same(got[rid], alone)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_staggered_large_batches_match_alone(rt, ctx, grids, precision):
+    """Two requests of 65,536 rays (the smallest batch that starts
+    staggered) that cannot share a launch (different maximum group paths),
+    on a two-slot server whose slot buffers first held a small request.  The
+    first large launch grows its slot's buffers while the second waits for
+    that launch's one-lane phase to end; then both finish.  Every result
+    equals, bit for bit, its fan traced alone, fetched to host memory for
+    one request and to device memory for the other."""
+    big = synth.Fan(30.0, 110.0, 0.0, np.linspace(3.0, 65.0, 64), np.linspace(-60.0, 60.0, 128),
+                    np.array([5.0, 7.5, 10.0, 12.5]), (1, -1))
+    small = synth.Fan(30.0, 110.0, 0.0, np.linspace(5.0, 60.0, 10), np.linspace(-30.0, 30.0, 10),
+                      np.array([8.0]), (1,))
+    assert rt.fan_count(big) == 1 << 16
+    o_a = opts(precision)
+    o_b = dict(opts(precision), max_group_km=3000.0)
+    srv = rt.Server(ctx, n_slots=2, mem_budget_bytes=64 << 20)
+    try:
+        s_id = srv.submit(grids[0], small, **o_a)
+        d_small = drain(srv, 1)
+        srv.fetch(s_id, d_small[s_id]["n_rays"])
+        a_id = srv.submit(grids[0], big, **o_a)
+        b_id = srv.submit(grids[1], big, **o_b)
+        # the second large batch waits (its one-lane phase alone takes
+        # milliseconds; these calls return within microseconds)
+        st = srv.stats()
+        assert st["running"] == 1 and st["queued"] == 1, st
+        done = drain(srv, 2)
+        got_a = srv.fetch(a_id, done[a_id]["n_rays"])
+        got_b = srv.fetch(b_id, done[b_id]["n_rays"], device=True)
+        got_b = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in got_b.items()}
+        assert srv.stats() == dict(queued=0, running=0, arena_used=0)
+    finally:
+        srv.close()
+    for rid, g, o, got in ((a_id, grids[0], o_a, got_a), (b_id, grids[1], o_b, got_b)):
+        alone = rt.trace(ctx, g, big, **o)
+        assert done[rid]["total_steps"] == alone["total_steps"]
+        same(got, alone)
+
+
 def test_admission_by_memory(rt, ctx, grids):
     """An arena that holds one request at a time: all requests still finish,
     in submission order, with the same results."""
