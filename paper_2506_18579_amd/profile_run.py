@@ -15,9 +15,11 @@ import numpy as np
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("ionogram", "aniso", "iso", "serving"), default="ionogram",
+    ap.add_argument("--workload", choices=("ionogram", "aniso", "iso", "serving", "sweeps8"),
+                    default="ionogram",
                     help="serving: the 400-request serving mix, every request queued at once "
-                         "(the saturation run of the benchmark), through the request server")
+                         "(the saturation run of the benchmark), through the request server; "
+                         "sweeps8: eight ionogram sweeps (two per snapshot) queued at once there")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0)
@@ -42,7 +44,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(f"copy {a.copy_mb} MiB read + {a.copy_mb} MiB write", flush=True)
-    if a.workload == "serving":
+    if a.workload in ("serving", "sweeps8"):
         serving(a, rtgd, synth)
         return
     wl = {"ionogram": lambda: synth.ionogram_workload(0),
@@ -79,19 +81,28 @@ def main():
 def serving(a, rtgd, synth):
     """The benchmark's serving mix at saturation: 400 requests (90 % ray fans
     of 1-20,000 rays, 10 % ionogram syntheses) over 4 resident snapshots,
-    all queued at t = 0, `reps` times after a warm-up of 8 requests."""
+    all queued at t = 0, `reps` times after a warm-up of 8 requests; or
+    (sweeps8) eight 112,400-ray ionogram sweeps, two per snapshot, queued at
+    t = 0."""
     from paper_2506_18579_amd import serve
     ctx = rtgd.Context(0)
     snaps = [rtgd.Grid(ctx, synth.ionosphere_grid(synth.GEOM_ANISO, s)) for s in range(4)]
     reqs = synth.serving_requests(400, seed=1234, n_snapshots=4, max_rays=20000, qps=200.0,
                                   ionogram_fraction=0.1)
-    burst = [dict(q, t_arrive=0.0) for q in reqs]
     o = dict(step_km=1.0, max_group_km=4000.0, exit_h_km=600.0, precision=a.precision)
     srv = rtgd.Server(ctx, mem_budget_bytes=256 << 20)
     serve.replay(srv, snaps, reqs[:8], o)
+    if a.workload == "sweeps8":
+        wl = synth.ionogram_workload(0)
+        burst = [dict(t_arrive=0.0, snapshot=s % 4, fan=wl.fan) for s in range(8)]
+        o = dict(step_km=wl.step_km, max_group_km=wl.max_group_km, exit_h_km=wl.exit_km, precision=a.precision)
+        name = "eight_ionogram_sweeps"
+    else:
+        burst = [dict(q, t_arrive=0.0) for q in reqs]
+        name = "serving_400_requests"
     for i in range(a.reps):
         r = serve.replay(srv, snaps, burst, o)
-        print(json.dumps({"rep": i, "workload": "serving_400_requests", "precision": a.precision,
+        print(json.dumps({"rep": i, "workload": name, "precision": a.precision,
                           "wall_ms": r["wall_s"] * 1e3, "ray_steps": int(r["ray_steps"].sum()),
                           "ray_steps_per_s": float(r["ray_steps"].sum() / r["wall_s"])}), flush=True)
     srv.close()
